@@ -1,0 +1,44 @@
+"""FP64 CPU oracle for block-sparse tensor contraction over tiled, spin-blocked index spaces.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product package may import, call, link or execute
+this package; only the test suite, the smoke check and the benchmark's CPU-baseline leg use it.
+It shares no code with the HIP path: its own tiling, its own block-storage rule, its own
+contraction loop.  It is deliberately plain and slow: nested Python loops over tiles, with one
+``numpy.einsum`` per surviving tile pair, in float64.
+
+What it follows (arXiv 2201.01257, "TAMM: Tensor Algebra for Many-body Methods"):
+
+* tiled index spaces, fixed or explicit tile lists, tensors as blocks over the Cartesian
+  product of tiles (Sec. III-A, Fig. 1);
+* spin-blocked storage where structurally zero blocks are not stored, and a user-supplied
+  non-zero check used both for allocation and for operation execution (Sec. III-A);
+* the contraction operation ``C(..) += alpha * A(..) * B(..)`` of the operation grammar
+  (Sec. III-A, Fig. 3, grammar rule 8) and its ``=`` / ``+=`` / ``-=`` forms;
+* the CCSD doubles terms, the intermediate factorisation of Eqs. (cc9)-(cc11) and its TAMM
+  form (Eq. tamm_cc11), spin-explicit sub-spaces (Eq. tamm_cc-Spin), Sec. IV-A-1;
+* the orbital-energy-denominator update that turns a doubles residual into new amplitudes
+  (the Jacobi step of CD-CCSD, named in Sec. IV-B-1).
+
+Readings taken where the paper is silent are listed in the module docstrings they affect.
+
+Pins: every function here is checked by the ``-m "not gpu"`` tests against something other
+than itself (dense brute force, a BLAS GEMM special case, the Eq. (cc9)-(cc11) identity,
+closed-form block counts, the worked tiling example of Fig. 1, invariants, finite
+differences).  The mixed-precision error model has no exact pin (parity unpinned beyond the
+tolerance it states).
+"""
+
+from .tiling import Space, spin_conserving
+from .blocksparse import BlockTensor, contract, screen, denominator_update, parse_labels
+from .adjoint import contract_vjp
+
+__all__ = [
+    "Space",
+    "spin_conserving",
+    "BlockTensor",
+    "contract",
+    "screen",
+    "denominator_update",
+    "parse_labels",
+    "contract_vjp",
+]
