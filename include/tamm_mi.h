@@ -1,0 +1,250 @@
+/* tamm_mi.h -- C ABI of the MI355X (gfx950) block-sparse tensor contraction library.
+ *
+ * The library implements the tensor-contraction operation of TAMM (arXiv 2201.01257,
+ * "TAMM: Tensor Algebra for Many-body Methods") for one GPU:
+ *
+ *   - tiled index spaces with a spin attribute per tile (Sec. III-A, Fig. 1);
+ *   - block-sparse tensors that store only structurally non-zero blocks, decided by spin
+ *     symmetry or by a user-supplied non-zero check (Sec. III-A; non-zero-only block storage
+ *     is the third distribution scheme of Sec. III-B);
+ *   - the contraction C(..) = beta*C(..) + alpha * A(..) * B(..) of the operation grammar
+ *     (Sec. III-A, Fig. 3 rule 8, Fig. 4), with "=" as beta = 0, "+=" as beta = 1 and "-=" as
+ *     alpha -> -alpha;
+ *   - deferred execution: an operation is analysed once into a plan and executed many times
+ *     (the queue-then-execute scheduler of Sec. III-A, Fig. 4, and Sec. III-B), and several
+ *     independent plans can be executed as one group.
+ *
+ * Conventions for every entry point:
+ *   - Every function returns a tamm_status (0 = success).  Nothing throws or aborts across
+ *     the ABI.  On failure tamm_last_error() returns a message for the calling thread.
+ *   - Device memory is owned by the caller.  The library never allocates device memory: the
+ *     caller binds tensor storage (tamm_tensor_bind) and plan/group workspace
+ *     (tamm_plan_bind_workspace, tamm_group_bind_workspace).  Handles own host metadata only.
+ *   - Asynchronous calls take a hipStream_t (passed as void*; NULL = the null stream), enqueue
+ *     their kernels on it and return without synchronising.  HIP launch errors are reported
+ *     as TAMM_ERR_HIP.
+ *   - Handles are not thread-safe; distinct handles may be used from distinct threads.
+ *   - Labels are strings of ASCII letters, one per tensor dimension, no letter twice in one
+ *     tensor.  In a contraction every letter appears in exactly two of the three tensors and
+ *     binds the same tiled space (same tile sizes and spins) wherever it appears.
+ */
+#ifndef TAMM_MI_H
+#define TAMM_MI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TAMM_OK = 0,
+  TAMM_ERR_ARG = -1,         /* null handle/pointer, negative size, out-of-range value        */
+  TAMM_ERR_LABEL = -2,       /* label string malformed, or a letter binds different spaces    */
+  TAMM_ERR_SHAPE = -3,       /* rank mismatch between a label string and its tensor           */
+  TAMM_ERR_SPARSITY = -4,    /* block structure inconsistent with the request                 */
+  TAMM_ERR_UNSUPPORTED = -5, /* valid request the library does not implement                  */
+  TAMM_ERR_UNBOUND = -6,     /* tensor storage or workspace not bound, or bound too small     */
+  TAMM_ERR_WORKSPACE = -7,   /* workspace pointer misaligned or too small                     */
+  TAMM_ERR_HIP = -8          /* a HIP runtime call failed                                     */
+} tamm_status;
+
+/* Compute precision of a contraction.  Storage is always IEEE float64.
+ *   F64     : float64 products and float64 accumulation (v_mfma_f64_16x16x4_f64).
+ *   F32     : operands rounded to float32 (round to nearest even), float32 matrix-core
+ *             products and float32 accumulation inside a K chunk, chunk sums added in float64,
+ *             float64 epilogue.
+ *   BF16X3  : each operand split into three bfloat16 terms x = b0 + b1 + b2 (b0 = bf16(x),
+ *             b1 = bf16(x - b0), b2 = bf16(x - b0 - b1)); the six products b_i*b_j with
+ *             i + j <= 2 on bfloat16 matrix cores with float32 accumulation inside a K chunk,
+ *             chunk sums added in float64, float64 epilogue.
+ *   BF16X3_EXACT : as BF16X3, except that the leading term of every row of A and every column
+ *             of B is a fixed-point slice aligned to the row/column maximum exponent, so that
+ *             the dominant product is accumulated exactly inside a K chunk (see the design notes
+ *             for its error model).
+ */
+typedef enum { TAMM_PREC_F64 = 0, TAMM_PREC_F32 = 1, TAMM_PREC_BF16X3 = 2, TAMM_PREC_BF16X3_EXACT = 3 } tamm_precision;
+
+/* User non-zero check (Sec. III-A: a user-defined non-zero check used both for allocation and
+ * for operation execution).  Called once per tile tuple when a tensor is created, with the
+ * tile index and tile spin of every dimension.  Returns 1 if the block is stored, 0 if it is a
+ * structural zero.  When NULL, the spin rule is used: a block of a rank-2k tensor is stored
+ * iff the spins of its first k tiles add up to the spins of its last k tiles; blocks of
+ * odd-rank tensors are always stored. */
+typedef int (*tamm_nonzero_fn)(const int32_t* tile_idx, const int8_t* tile_spin, int32_t rank, void* user);
+
+typedef struct tamm_space tamm_space;
+typedef struct tamm_tensor tamm_tensor;
+typedef struct tamm_plan tamm_plan;
+typedef struct tamm_group tamm_group;
+
+/* Message describing the last failure on the calling thread ("" if none).  Valid until the
+ * next library call on this thread. */
+const char* tamm_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t tamm_version(void);
+
+/* ------------------------------------------------------------------------------------------
+ * Tiled index spaces (Sec. III-A, Fig. 1).
+ * ------------------------------------------------------------------------------------------ */
+
+/* Explicit tiling: ntiles tiles of the given positive sizes, covering [0, sum of sizes) in
+ * order, each with a spin code (0 = alpha, 1 = beta; NULL = all 0).  Arrays are read during
+ * the call only.  ERR_ARG on ntiles <= 0, a non-positive size or a null output pointer. */
+int tamm_space_create(const int64_t* tile_sizes, const int8_t* tile_spin, int32_t ntiles, tamm_space** out);
+
+/* Fixed-size tiling of one range (Fig. 1, "tN{N, 10}"): full tiles then one shorter remainder
+ * tile, all with spin 0. */
+int tamm_space_create_fixed(int64_t extent, int64_t tile, tamm_space** out);
+
+/* Spin-blocked tiling: the alpha sub-space [0, n_alpha) then the beta sub-space, each tiled on
+ * its own with tile size min(tile, sub-space size), remainder tile last; tiles never straddle
+ * the two sub-spaces.  An empty sub-space contributes no tiles. */
+int tamm_space_create_spin(int64_t n_alpha, int64_t n_beta, int64_t tile, tamm_space** out);
+
+/* Number of tiles and total extent. */
+int tamm_space_info(const tamm_space* s, int32_t* ntiles, int64_t* extent);
+
+/* Copy out tile sizes, tile start offsets and tile spins (each array ntiles long; any may be
+ * NULL). */
+int tamm_space_tiles(const tamm_space* s, int64_t* tile_sizes, int64_t* tile_offsets, int8_t* tile_spin);
+
+int tamm_space_destroy(tamm_space* s);
+
+/* ------------------------------------------------------------------------------------------
+ * Block-sparse tensors (Sec. III-A; non-zero-only storage, Sec. III-B).
+ *
+ * Storage layout: the stored blocks back to back in lexicographic order of their tile tuples;
+ * each block row-major in the tensor's own dimension order with extents equal to its tile
+ * sizes; float64 elements.  A tensor copies what it needs from its spaces, so spaces may be
+ * destroyed after tensor creation.
+ * ------------------------------------------------------------------------------------------ */
+
+/* rank in [1, 8].  nonzero NULL selects the spin rule (see tamm_nonzero_fn). */
+int tamm_tensor_create(tamm_space* const* dims, int32_t rank, tamm_nonzero_fn nonzero, void* user, tamm_tensor** out);
+
+/* Number of stored elements and bytes (stored blocks only). */
+int tamm_tensor_numel(const tamm_tensor* t, int64_t* numel);
+int tamm_tensor_nbytes(const tamm_tensor* t, size_t* bytes);
+
+/* Stored block table: *nblocks receives the count; if tile_idx is not NULL it receives
+ * nblocks*rank tile indices (block-major), and if elem_off is not NULL it receives the element
+ * offset of each block in the storage. */
+int tamm_tensor_blocks(const tamm_tensor* t, int64_t* nblocks, int32_t* tile_idx, int64_t* elem_off);
+
+/* Bind caller-owned device storage (not owned, not freed by the library).  ERR_UNBOUND if
+ * bytes is smaller than tamm_tensor_nbytes; ERR_ARG if dev_ptr is NULL while numel > 0 or is
+ * not 8-byte aligned. */
+int tamm_tensor_bind(tamm_tensor* t, void* dev_ptr, size_t bytes);
+
+int tamm_tensor_destroy(tamm_tensor* t);
+
+/* ------------------------------------------------------------------------------------------
+ * Contraction plans (Sec. III-A, Fig. 3 rule 8; the block non-zero analysis of Sec. III-A).
+ *
+ * out(out_lbl) = beta * out(out_lbl) + alpha * lhs(lhs_lbl) * rhs(rhs_lbl), summed over the
+ * letters of lhs and rhs that out does not carry, on the stored blocks of out.  Operands are
+ * read as dense tensors whose unstored blocks are zero.  A stored out block that no tile pair
+ * reaches becomes beta * out (0 when beta == 0).  Tile pairs whose out block is not stored
+ * (possible only with a user non-zero check) are dropped and counted in the plan statistics.
+ * beta == 0 never reads out (NaN/Inf in out do not propagate).
+ *
+ * The three tensors must outlive the plan; out must not alias lhs or rhs storage.  Plan
+ * creation is host-only (no GPU call).
+ * ------------------------------------------------------------------------------------------ */
+int tamm_plan_create(tamm_tensor* out, const char* out_lbl, const tamm_tensor* lhs, const char* lhs_lbl,
+                     const tamm_tensor* rhs, const char* rhs_lbl, tamm_precision precision, tamm_plan** plan);
+
+/* Device workspace needed by the plan (bytes, 256-byte aligned start required). */
+int tamm_plan_workspace_size(const tamm_plan* p, size_t* bytes);
+
+/* Bind caller-owned device workspace and upload the plan's static tables into it
+ * (synchronous copy).  ERR_WORKSPACE if too small or misaligned. */
+int tamm_plan_bind_workspace(tamm_plan* p, void* dev_ptr, size_t bytes);
+
+typedef struct {
+  int64_t out_blocks;     /* stored blocks of out                                              */
+  int64_t candidates;     /* out blocks x tile tuples of the summed labels                     */
+  int64_t tasks;          /* surviving tile pairs (host structural count)                      */
+  int64_t dropped;        /* surviving pairs whose out block is not stored                     */
+  double useful_flops;    /* 2 * sum over surviving tile triples of the product of extents     */
+  double algorithmic_bytes; /* 8 * (stored lhs + stored rhs + 2 * stored out elements)         */
+  int64_t work_items;     /* output macro-tiles times K splits scheduled by the kernel         */
+  int32_t kernel_config;  /* active kernel configuration id                                    */
+  int32_t k_splits;       /* K splits per output macro-tile                                    */
+} tamm_plan_stats;
+
+int tamm_plan_stats_get(const tamm_plan* p, tamm_plan_stats* s);
+
+/* Kernel configurations available for this plan's precision: *count receives the number; ids
+ * are 0..count-1.  tamm_plan_set_config selects one (the autotuner uses this) and k_splits
+ * >= 1 splits each output tile's K range into that many deterministic partial sums (0 = let
+ * the library choose).  Changing the configuration requires re-querying the workspace size
+ * and re-binding. */
+int tamm_plan_config_count(const tamm_plan* p, int32_t* count);
+int tamm_plan_set_config(tamm_plan* p, int32_t config, int32_t k_splits);
+/* Human-readable name of a configuration (static string), e.g. "f64_m128n64_k16". */
+const char* tamm_config_name(int32_t precision, int32_t config);
+
+/* Enqueue the whole operation on stream: tamm_plan_screen then tamm_plan_contract.
+ * Requires bound storage on all three tensors and a bound workspace. */
+int tamm_plan_execute(tamm_plan* p, double alpha, double beta, void* stream);
+
+/* The two halves of tamm_plan_execute.  tamm_plan_screen enqueues the GPU tile-pair screening,
+ * which writes the surviving pair list of every stored out block into the workspace (the block
+ * non-zero analysis of Sec. III-A).  tamm_plan_contract enqueues the contraction kernel (and,
+ * with K splits, the ordered reduction) that consumes the last screened pair list; it fails with
+ * ERR_UNBOUND if the plan was never screened on its current workspace. */
+int tamm_plan_screen(tamm_plan* p, void* stream);
+int tamm_plan_contract(tamm_plan* p, double alpha, double beta, void* stream);
+
+/* Copy the GPU screening results of the last execution to the host (synchronises stream):
+ * per stored out block (in storage order) the number of surviving pairs; and optionally the
+ * K tile-tuple index of every surviving pair (out block major, pairs in lexicographic order,
+ * sum(counts) entries).  For tests and statistics. */
+int tamm_plan_screen_result(tamm_plan* p, void* stream, int32_t* counts, int32_t* k_tuple_idx);
+
+int tamm_plan_destroy(tamm_plan* p);
+
+/* ------------------------------------------------------------------------------------------
+ * Groups: many independent plans executed as one persistent launch (the single-GPU analogue
+ * of running the operations of one scheduler level together, Sec. III-B).  Plans must be
+ * bound to distinct output tensors (no two plans of a group write the same storage) and must
+ * all use TAMM_PREC_F64.  Plans must outlive the group; the group uses its own workspace
+ * (the plans' own workspaces are not needed for group execution).
+ * ------------------------------------------------------------------------------------------ */
+int tamm_group_create(tamm_plan* const* plans, int32_t n, tamm_group** g);
+int tamm_group_workspace_size(const tamm_group* g, size_t* bytes);
+int tamm_group_bind_workspace(tamm_group* g, void* dev_ptr, size_t bytes);
+/* Select the group's kernel configuration and persistent grid size (0 = one workgroup slot per
+ * compute unit times the occupancy the configuration allows). */
+int tamm_group_set_config(tamm_group* g, int32_t config, int32_t grid);
+/* alpha and beta are host arrays of n values, read during the call. */
+int tamm_group_execute(tamm_group* g, const double* alpha, const double* beta, void* stream);
+int tamm_group_destroy(tamm_group* g);
+
+/* ------------------------------------------------------------------------------------------
+ * Orbital-energy denominator update (the Jacobi step of CD-CCSD named in Sec. IV-B-1, which
+ * turns a residual into amplitudes):
+ *   out[p] = in[p] / D(p),  D(p) = sum of energy[d][p_d] over dims with sign[d] > 0, in
+ *   dimension order, then minus energy[d][p_d] over dims with sign[d] < 0, in dimension order
+ *   (for R[a,b,i,j] with signs (-,-,+,+): ((e_i + e_j) - e_a) - e_b).  IEEE float64 division
+ *   (correctly rounded), over the stored blocks.
+ * energy: host array of rank device pointers (read during the call), each indexing the full
+ * untiled range of its dimension; a dimension with sign 0 takes no part and may pass NULL.
+ * out and in must have identical block structure and may be the same tensor.  workspace:
+ * caller-owned device memory of tamm_denominator_workspace_size bytes, 256-byte aligned; the
+ * call enqueues the upload of the block metadata into it, so it must not be reused by another
+ * call before this one's work on the stream has run.
+ * ------------------------------------------------------------------------------------------ */
+int tamm_denominator_workspace_size(const tamm_tensor* t, size_t* bytes);
+int tamm_denominator_update(tamm_tensor* out, const tamm_tensor* in, const double* const* energy, const int8_t* sign,
+                            void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TAMM_MI_H */

@@ -29,13 +29,14 @@ tolerance it states).
 """
 
 from .tiling import Space, spin_conserving
-from .blocksparse import BlockTensor, contract, screen, denominator_update, parse_labels
+from .blocksparse import BlockTensor, LazyBlocks, contract, screen, denominator_update, parse_labels
 from .adjoint import contract_vjp
 
 __all__ = [
     "Space",
     "spin_conserving",
     "BlockTensor",
+    "LazyBlocks",
     "contract",
     "screen",
     "denominator_update",

@@ -43,6 +43,22 @@ def _default_nonzero(tiles: Tile, spins: Tile) -> bool:
     return spin_conserving(spins)
 
 
+class LazyBlocks(dict):
+    """Block dictionary that produces a stored block on first access (inputs too large to hold).
+
+    ``fill(tile tuple) -> block``; used to feed sampled runs of large problems.
+    """
+
+    def __init__(self, fill: Callable[[Tile], np.ndarray]):
+        super().__init__()
+        self._fill = fill
+
+    def __missing__(self, key):
+        v = np.asarray(self._fill(key), dtype=np.float64)
+        self[key] = v
+        return v
+
+
 class BlockTensor:
     """Stored blocks of a tensor over tiled spaces, keyed by tile tuples (row-major blocks)."""
 
@@ -152,14 +168,21 @@ def _label_spaces(out, out_lbl, lhs, lhs_lbl, rhs, rhs_lbl) -> Dict[str, Space]:
 
 
 def contract(out: BlockTensor, out_lbl: str, lhs: BlockTensor, lhs_lbl: str, rhs: BlockTensor, rhs_lbl: str,
-             alpha: float = 1.0, beta: float = 0.0) -> BlockTensor:
-    """Return a new tensor: beta * out + alpha * (lhs contracted with rhs), on out's stored blocks."""
+             alpha: float = 1.0, beta: float = 0.0, out_tiles=None) -> BlockTensor:
+    """Return a new tensor: beta * out + alpha * (lhs contracted with rhs), on out's stored blocks.
+
+    ``out_tiles`` restricts the work to the listed stored output blocks (sampling a large
+    problem); the result then holds only those blocks.
+    """
     _, _, k_lbl = parse_labels(out_lbl, lhs_lbl, rhs_lbl)
     spaces = _label_spaces(out, out_lbl, lhs, lhs_lbl, rhs, rhs_lbl)
     spec = f"{lhs_lbl},{rhs_lbl}->{out_lbl}"
     k_ranges = [range(spaces[c].ntiles) for c in k_lbl]
     result = BlockTensor(out.spaces, out.nonzero)
-    for ot in out.stored_tiles():
+    todo = out.stored_tiles() if out_tiles is None else [tuple(t) for t in out_tiles]
+    for ot in todo:
+        if not out.is_stored(ot):
+            raise ValueError(f"output block {ot} is not stored")
         acc = np.zeros(out.block_shape(ot))
         tile_of = dict(zip(out_lbl, ot))
         for kt in product(*k_ranges):

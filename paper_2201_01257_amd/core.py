@@ -1,0 +1,339 @@
+"""Python binding of the C ABI: tiled spaces, block-sparse tensors on the GPU, contraction plans.
+
+Argument marshalling only: every step of a contraction (screening, gathers, MFMA products,
+epilogue) runs in the HIP library.  PyTorch supplies device memory and the current stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _lib
+from ._lib import NONZERO_FN, PlanStats, TammError, check, load
+
+PRECISIONS = {"f64": 0, "f32": 1, "bf16x3": 2, "bf16x3_exact": 3}
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def current_stream_handle():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _aligned_workspace(nbytes: int, device):
+    """A uint8 device buffer with a 256-byte aligned start; returns (owner, pointer)."""
+    torch = _torch()
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    ptr = buf.data_ptr()
+    pad = (-ptr) % 256
+    return buf, ptr + pad
+
+
+class Space:
+    """A tiled index space (Sec. III-A, Fig. 1), owned by the C library."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+        lib = load()
+        n = ctypes.c_int32()
+        ext = ctypes.c_int64()
+        check(lib.tamm_space_info(self._h, ctypes.byref(n), ctypes.byref(ext)))
+        self.ntiles = n.value
+        self.extent = ext.value
+        self.sizes = np.zeros(self.ntiles, dtype=np.int64)
+        self.offsets = np.zeros(self.ntiles, dtype=np.int64)
+        self.spins = np.zeros(self.ntiles, dtype=np.int8)
+        check(lib.tamm_space_tiles(self._h, self.sizes.ctypes.data, self.offsets.ctypes.data, self.spins.ctypes.data))
+
+    @classmethod
+    def spin(cls, n_alpha: int, n_beta: int, tile: int) -> "Space":
+        h = ctypes.c_void_p()
+        check(load().tamm_space_create_spin(n_alpha, n_beta, tile, ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def fixed(cls, extent: int, tile: int) -> "Space":
+        h = ctypes.c_void_p()
+        check(load().tamm_space_create_fixed(extent, tile, ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def explicit(cls, sizes: Sequence[int], spins: Optional[Sequence[int]] = None) -> "Space":
+        s = np.ascontiguousarray(np.asarray(sizes, dtype=np.int64))
+        sp = None if spins is None else np.ascontiguousarray(np.asarray(spins, dtype=np.int8))
+        h = ctypes.c_void_p()
+        check(load().tamm_space_create(s.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       None if sp is None else sp.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                                       len(s), ctypes.byref(h)))
+        return cls(h.value)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib._lib is not None:
+            _lib._lib.tamm_space_destroy(self._h)
+            self._h = None
+
+
+class Tensor:
+    """A block-sparse float64 tensor whose stored blocks live in one device buffer.
+
+    ``nonzero(tile_idx, tile_spins) -> bool`` overrides the spin rule.  ``device=None`` creates
+    the structure only (no storage), which is enough for planning on a machine without a GPU.
+    """
+
+    def __init__(self, spaces: Sequence[Space], nonzero: Optional[Callable] = None, device="cuda"):
+        lib = load()
+        self.spaces = list(spaces)
+        self.rank = len(self.spaces)
+        arr = (ctypes.c_void_p * self.rank)(*[s._h.value for s in self.spaces])
+        h = ctypes.c_void_p()
+        cb = None
+        if nonzero is not None:
+            def _cb(tiles, spins, rank, user):
+                t = tuple(tiles[i] for i in range(rank))
+                s = tuple(spins[i] for i in range(rank))
+                return 1 if nonzero(t, s) else 0
+            cb = NONZERO_FN(_cb)
+        check(lib.tamm_tensor_create(arr, self.rank, ctypes.cast(cb, ctypes.c_void_p) if cb else None, None,
+                                     ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int64()
+        check(lib.tamm_tensor_numel(self._h, ctypes.byref(n)))
+        self.numel = n.value
+        nb = ctypes.c_int64()
+        check(lib.tamm_tensor_blocks(self._h, ctypes.byref(nb), None, None))
+        self.nblocks = nb.value
+        self.block_tiles = np.zeros((self.nblocks, self.rank), dtype=np.int32)
+        self.block_off = np.zeros(self.nblocks, dtype=np.int64)
+        if self.nblocks:
+            check(lib.tamm_tensor_blocks(self._h, ctypes.byref(nb), self.block_tiles.ctypes.data,
+                                         self.block_off.ctypes.data))
+        self.data = None
+        self._plans: Dict[tuple, tuple] = {}
+        if device is not None:
+            torch = _torch()
+            self.data = torch.zeros(max(self.numel, 1), dtype=torch.float64, device=device)
+            self.bind(self.data)
+
+    def bind(self, storage):
+        """Bind a float64 torch tensor with at least ``numel`` elements as the storage."""
+        torch = _torch()
+        if storage.dtype != torch.float64 or not storage.is_contiguous() or storage.numel() < self.numel:
+            raise ValueError("storage must be a contiguous float64 tensor with at least numel elements")
+        self.data = storage
+        check(load().tamm_tensor_bind(self._h, ctypes.c_void_p(storage.data_ptr()), storage.numel() * 8))
+
+    # -- block geometry -------------------------------------------------------------------
+    def block_lo_ext(self, b: int) -> Tuple[Tuple[int, ...], Tuple[int, ...]]:
+        t = self.block_tiles[b]
+        lo = tuple(int(self.spaces[d].offsets[t[d]]) for d in range(self.rank))
+        ext = tuple(int(self.spaces[d].sizes[t[d]]) for d in range(self.rank))
+        return lo, ext
+
+    @property
+    def shape(self) -> Tuple[int, ...]:
+        return tuple(s.extent for s in self.spaces)
+
+    # -- host <-> device ------------------------------------------------------------------
+    def fill_blocks(self, fn: Callable[[Tuple[int, ...], Tuple[int, ...], np.ndarray], None],
+                    chunk_bytes: int = 256 << 20):
+        """Fill every stored block on the host with ``fn(lo, ext, out)`` and upload it.
+
+        ``out`` is a C-contiguous float64 array of shape ``ext`` to be written in place.
+        Blocks are staged through a pinned host buffer of at most ``chunk_bytes``.
+        """
+        torch = _torch()
+        if self.data is None:
+            raise RuntimeError("tensor has no device storage")
+        if self.numel == 0:
+            return
+        cap = max(chunk_bytes // 8, 1)
+        largest = max(int(np.prod(self.block_lo_ext(b)[1])) for b in range(self.nblocks))
+        cap = max(cap, largest)
+        pinned = self.data.is_cuda
+        stage = torch.empty(min(cap, self.numel), dtype=torch.float64, pin_memory=pinned)
+        host = stage.numpy()
+        b = 0
+        while b < self.nblocks:
+            start = int(self.block_off[b])
+            e = b
+            end = start
+            while e < self.nblocks:
+                n = int(np.prod(self.block_lo_ext(e)[1]))
+                if end + n - start > cap:
+                    break
+                end += n
+                e += 1
+            for j in range(b, e):
+                lo, ext = self.block_lo_ext(j)
+                off = int(self.block_off[j]) - start
+                n = int(np.prod(ext))
+                fn(lo, ext, host[off:off + n].reshape(ext))
+            self.data[start:end].copy_(stage[:end - start], non_blocking=False)
+            b = e
+
+    def from_dense(self, dense: np.ndarray):
+        dense = np.asarray(dense, dtype=np.float64)
+        if dense.shape != self.shape:
+            raise ValueError(f"dense shape {dense.shape} != {self.shape}")
+
+        def fn(lo, ext, out):
+            out[...] = dense[tuple(slice(l, l + e) for l, e in zip(lo, ext))]
+
+        self.fill_blocks(fn)
+        return self
+
+    def to_host(self) -> np.ndarray:
+        torch = _torch()
+        torch.cuda.synchronize()
+        return self.data[: self.numel].cpu().numpy()
+
+    def to_blocks(self) -> Dict[Tuple[int, ...], np.ndarray]:
+        flat = self.to_host()
+        out = {}
+        for b in range(self.nblocks):
+            lo, ext = self.block_lo_ext(b)
+            off = int(self.block_off[b])
+            out[tuple(int(x) for x in self.block_tiles[b])] = flat[off:off + int(np.prod(ext))].reshape(ext)
+        return out
+
+    def to_dense(self) -> np.ndarray:
+        d = np.zeros(self.shape)
+        flat = self.to_host()
+        for b in range(self.nblocks):
+            lo, ext = self.block_lo_ext(b)
+            off = int(self.block_off[b])
+            d[tuple(slice(l, l + e) for l, e in zip(lo, ext))] = flat[off:off + int(np.prod(ext))].reshape(ext)
+        return d
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib._lib is not None:
+            self._plans = {}
+            _lib._lib.tamm_tensor_destroy(self._h)
+            self._h = None
+
+
+class Plan:
+    """A contraction out(ol) = beta*out + alpha * lhs(ll) * rhs(rl), analysed once."""
+
+    def __init__(self, out: Tensor, ol: str, lhs: Tensor, ll: str, rhs: Tensor, rl: str, precision: str = "f64",
+                 bind: bool = True):
+        self.out, self.lhs, self.rhs = out, lhs, rhs  # kept alive as long as the plan
+        self.labels = (ol, ll, rl)
+        self.precision = precision
+        h = ctypes.c_void_p()
+        check(load().tamm_plan_create(out._h, ol.encode(), lhs._h, ll.encode(), rhs._h, rl.encode(),
+                                      PRECISIONS[precision], ctypes.byref(h)))
+        self._h = h
+        self._ws = None
+        if bind and out.data is not None:
+            self.bind_workspace()
+
+    def workspace_size(self) -> int:
+        n = ctypes.c_size_t()
+        check(load().tamm_plan_workspace_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    def bind_workspace(self):
+        device = self.out.data.device
+        self._ws, ptr = _aligned_workspace(self.workspace_size(), device)
+        check(load().tamm_plan_bind_workspace(self._h, ctypes.c_void_p(ptr), self.workspace_size()))
+
+    def stats(self) -> dict:
+        s = PlanStats()
+        check(load().tamm_plan_stats_get(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in PlanStats._fields_}
+
+    def config_count(self) -> int:
+        n = ctypes.c_int32()
+        check(load().tamm_plan_config_count(self._h, ctypes.byref(n)))
+        return n.value
+
+    def set_config(self, config: int, k_splits: int = 0):
+        check(load().tamm_plan_set_config(self._h, config, k_splits))
+        if self.out.data is not None:
+            self.bind_workspace()
+
+    def config_name(self, config: Optional[int] = None) -> str:
+        c = self.stats()["kernel_config"] if config is None else config
+        return load().tamm_config_name(PRECISIONS[self.precision], c).decode()
+
+    def execute(self, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        s = current_stream_handle() if stream is None else stream
+        check(load().tamm_plan_execute(self._h, float(alpha), float(beta), s))
+
+    def screen(self, stream=None):
+        check(load().tamm_plan_screen(self._h, current_stream_handle() if stream is None else stream))
+
+    def contract(self, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        s = current_stream_handle() if stream is None else stream
+        check(load().tamm_plan_contract(self._h, float(alpha), float(beta), s))
+
+    def screen_result(self):
+        """Per stored out block: list of surviving K tile tuples (K labels in lhs order)."""
+        st = self.stats()
+        nob = st["out_blocks"]
+        counts = np.zeros(max(nob, 1), dtype=np.int32)
+        ol, ll, rl = self.labels
+        nk = len([c for c in ll if c not in ol])
+        ktiles = np.zeros(max(st["candidates"] * max(nk, 1), 1), dtype=np.int32)
+        check(load().tamm_plan_screen_result(self._h, current_stream_handle(), counts.ctypes.data, ktiles.ctypes.data))
+        res = []
+        w = 0
+        for b in range(nob):
+            lst = []
+            for _ in range(int(counts[b])):
+                lst.append(tuple(int(x) for x in ktiles[w:w + nk]))
+                w += nk
+            res.append(lst)
+        return res
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib._lib is not None:
+            _lib._lib.tamm_plan_destroy(self._h)
+            self._h = None
+
+
+def contract(out: Tensor, ol: str, lhs: Tensor, ll: str, rhs: Tensor, rl: str, alpha: float = 1.0,
+             beta: float = 0.0, precision: str = "f64") -> Plan:
+    """out(ol) = beta*out(ol) + alpha * lhs(ll) * rhs(rl) on the GPU, with a plan cache on ``out``."""
+    key = (ol, id(lhs), ll, id(rhs), rl, precision)
+    ent = out._plans.get(key)
+    if ent is None or ent[0] is not lhs or ent[1] is not rhs:
+        plan = Plan(out, ol, lhs, ll, rhs, rl, precision)
+        out._plans[key] = (lhs, rhs, plan)
+    else:
+        plan = ent[2]
+    plan.execute(alpha, beta)
+    return plan
+
+
+class Denominator:
+    """out = in / D with D from per-dimension orbital energies (device tensors) and signs."""
+
+    def __init__(self, out: Tensor, inp: Tensor, energies: Sequence, signs: Sequence[int]):
+        torch = _torch()
+        self.out, self.inp = out, inp
+        self.energies = [None if e is None else e.to(dtype=torch.float64).contiguous() for e in energies]
+        self.signs = np.ascontiguousarray(np.asarray(signs, dtype=np.int8))
+        n = ctypes.c_size_t()
+        check(load().tamm_denominator_workspace_size(out._h, ctypes.byref(n)))
+        self.ws_bytes = max(n.value, 256)
+        self._ws, self._ws_ptr = _aligned_workspace(self.ws_bytes, out.data.device)
+        self._eptr = (ctypes.c_void_p * out.rank)(*[(0 if e is None else e.data_ptr()) for e in self.energies])
+
+    def execute(self, stream=None):
+        s = current_stream_handle() if stream is None else stream
+        check(load().tamm_denominator_update(self.out._h, self.inp._h, self._eptr,
+                                             self.signs.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                                             ctypes.c_void_p(self._ws_ptr), self.ws_bytes, s))
+
+
+__all__ = ["Space", "Tensor", "Plan", "contract", "Denominator", "TammError", "PRECISIONS"]

@@ -1,0 +1,132 @@
+// Internal data layouts shared by the host planner and the HIP kernels.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tamm {
+
+constexpr int kMaxRank = 8;
+
+// One stored block of the output tensor, as the contraction kernel and the screening kernel see
+// it.  The flattened M (out&A) and N (out&B) extents and the offset tables that map a flattened
+// row/column to an element offset inside the block are fixed by the block's tile sizes.
+struct OutBlockDesc {
+  int64_t c_off;    // element offset of the block in out's storage
+  int32_t mext;     // flattened M extent (product of M-label tile sizes)
+  int32_t next;     // flattened N extent
+  int32_t c_tabM;   // start of out's M offset table (int32 pool)
+  int32_t c_tabN;   // start of out's N offset table
+  int32_t a_tbase;  // A-operand tile-linear index contributed by the M labels
+  int32_t b_tbase;  // B-operand tile-linear index contributed by the N labels
+  int32_t a_cbase;  // A-operand shape-class id contributed by the M labels
+  int32_t b_cbase;  // B-operand shape-class id contributed by the N labels
+  int32_t pair_base;  // first slot of this block's surviving-pair list
+  int32_t pad;
+};
+static_assert(sizeof(OutBlockDesc) == 48, "OutBlockDesc layout");
+
+// One surviving tile pair of an output block, written by the screening kernel.
+struct PairDesc {
+  int64_t a_off;   // element offset of the A-operand block
+  int64_t b_off;   // element offset of the B-operand block
+  int32_t kext;    // flattened K extent of the pair
+  int32_t a_tabM;  // A's M offset table for this A block shape
+  int32_t a_tabK;  // A's K offset table
+  int32_t b_tabK;  // B's K offset table
+  int32_t b_tabN;  // B's N offset table
+  int32_t kt;      // index of the K tile tuple (lexicographic over the K labels)
+};
+static_assert(sizeof(PairDesc) == 40, "PairDesc layout");
+
+// One output macro-tile (or one K split of it) processed by one workgroup.
+struct WorkItem {
+  int32_t ob;     // output block
+  int32_t m0;     // first flattened row of the tile
+  int32_t n0;     // first flattened column
+  int32_t split;  // K split index (0 .. k_splits-1)
+};
+
+struct ScreenParams {
+  const int64_t* a_tile_off;  // per A tile-linear index: element offset, -1 = not stored
+  const int64_t* b_tile_off;
+  const OutBlockDesc* blocks;
+  PairDesc* pairs;
+  int32_t* counts;            // surviving pairs per output block
+  const int32_t* pool;        // int32 table pool
+  int32_t n_blocks;
+  int32_t n_kt;               // K tile tuples (pair capacity per output block)
+  int32_t nk;                 // number of K labels
+  int32_t k_ntiles[kMaxRank];
+  int32_t a_tstride[kMaxRank];
+  int32_t b_tstride[kMaxRank];
+  int32_t a_cstride[kMaxRank];
+  int32_t b_cstride[kMaxRank];
+  int32_t k_size_tab[kMaxRank];  // pool start of the K label's tile-size list
+  int32_t k_cls_tab[kMaxRank];   // pool start of the K label's tile size-class list
+  int32_t a_cls_tabM;            // pool start of the per-A-class table starts (M)
+  int32_t a_cls_tabK;
+  int32_t b_cls_tabK;
+  int32_t b_cls_tabN;
+};
+
+struct ContractParams {
+  const double* A;
+  const double* B;
+  double* C;
+  const OutBlockDesc* blocks;
+  const PairDesc* pairs;
+  const int32_t* counts;
+  const int32_t* pool;
+  const WorkItem* work;
+  double* partial;     // K-split partial tiles (work item major), or null
+  int32_t n_work;
+  int32_t k_splits;
+  double alpha;
+  double beta;
+};
+
+struct ReduceParams {
+  double* C;
+  const OutBlockDesc* blocks;
+  const int32_t* pool;
+  const WorkItem* work;   // all work items; the k_splits items of a tile are adjacent
+  const double* partial;
+  int32_t n_tiles;
+  int32_t k_splits;
+  int32_t tile_m;
+  int32_t tile_n;
+  double alpha;
+  double beta;
+};
+
+struct DenomParams {
+  double* out;
+  const double* in;
+  const int64_t* block_off;   // per stored block: element offset
+  const int32_t* block_tiles; // per stored block: rank tile indices
+  const int64_t* tile_offset; // per dim: untiled start of each tile (concatenated, dim starts below)
+  const int64_t* tile_size;
+  int32_t dim_tile_base[kMaxRank];
+  const double* energy[kMaxRank];
+  int8_t sign[kMaxRank];
+  int32_t rank;
+  int64_t n_blocks;
+};
+
+// Kernel configuration of the FP64 contraction kernel family.
+struct F64Config {
+  int mt, nt, kt, wgm, wgn;
+  const char* name;
+};
+
+int f64_config_count();
+const F64Config& f64_config(int id);
+
+// Launchers (kernels.hip).  Return hipError_t of the launch.
+hipError_t launch_screen(const ScreenParams& p, hipStream_t s);
+hipError_t launch_contract_f64(int config, bool a_kcontig, bool b_kcontig, const ContractParams& p, hipStream_t s);
+hipError_t launch_reduce(const ReduceParams& p, hipStream_t s);
+hipError_t launch_denominator(const DenomParams& p, int64_t max_block_elems, hipStream_t s);
+
+}  // namespace tamm

@@ -1,0 +1,159 @@
+"""Host-only checks of the C ABI (no GPU needed): exported symbols, tiling, block structure,
+label analysis, plan statistics against the oracle's screening counts, and error codes."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_01257_amd import _lib
+from paper_2201_01257_amd import core as tm
+from paper_2201_01257_amd.synth import TERMS
+
+lib = _lib.load()
+
+
+def test_library_exports_every_declared_function():
+    names = _lib.header_functions()
+    assert len(names) >= 30
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert missing == []
+    # every declared function has a ctypes signature in the binding and vice versa
+    assert sorted(_lib.SIGNATURES) == names
+
+
+@pytest.mark.parametrize("na,nb,tile", [(100, 100, 40), (20, 20, 40), (5, 5, 5), (37, 11, 16), (3, 0, 2), (0, 4, 3)])
+def test_spin_tiling_matches_oracle(na, nb, tile):
+    s = tm.Space.spin(na, nb, tile)
+    o = oracle.Space.spin_blocked(na, nb, tile)
+    assert list(s.sizes) == o.sizes and list(s.spins) == o.spins and list(s.offsets) == o.offsets
+
+
+def test_fig1_tiling_through_the_abi():
+    tM = tm.Space.explicit([10, 20])
+    tK = tm.Space.fixed(20, 5)
+    tN = tm.Space.fixed(100, 10)
+    dense = lambda t, s: True  # noqa: E731
+    A = tm.Tensor([tM, tK], nonzero=dense, device=None)
+    assert A.shape == (30, 20) and A.nblocks == 8
+    assert tN.ntiles == 10 and list(tK.sizes) == [5, 5, 5, 5]
+
+
+def test_block_table_matches_oracle_storage_order():
+    o = tm.Space.spin(3, 2, 2)
+    v = tm.Space.spin(4, 5, 3)
+    T = tm.Tensor([v, v, o, o], device=None)
+    os_ = oracle.Space.spin_blocked(3, 2, 2)
+    vs = oracle.Space.spin_blocked(4, 5, 3)
+    ref = oracle.BlockTensor([vs, vs, os_, os_])
+    stored = ref.stored_tiles()
+    assert [tuple(x) for x in T.block_tiles] == stored
+    sizes = [int(np.prod(ref.block_shape(t))) for t in stored]
+    assert list(T.block_off) == list(np.concatenate([[0], np.cumsum(sizes)[:-1]]))
+    assert T.numel == ref.nnz()
+
+
+def term_structures(term, occ, vir, device=None):
+    (on, op, ol), (ln, lp, ll), (rn, rp, rl), alpha = TERMS[term]
+    o = tm.Space.spin(*occ)
+    v = tm.Space.spin(*vir)
+    sp = lambda p: [o if c == "o" else v for c in p]  # noqa: E731
+    os_ = oracle.Space.spin_blocked(*occ)
+    vs = oracle.Space.spin_blocked(*vir)
+    osp = lambda p: [os_ if c == "o" else vs for c in p]  # noqa: E731
+    gpu = (tm.Tensor(sp(op), device=device), ol, tm.Tensor(sp(lp), device=device), ll, tm.Tensor(sp(rp), device=device), rl)
+    ref = (oracle.BlockTensor(osp(op)), ol, oracle.BlockTensor(osp(lp)), ll, oracle.BlockTensor(osp(rp)), rl)
+    return gpu, ref
+
+
+@pytest.mark.parametrize("term", list(TERMS))
+@pytest.mark.parametrize("occ,vir", [((20, 20, 40), (100, 100, 40)), ((5, 5, 5), (20, 20, 5)), ((3, 2, 2), (5, 4, 3))])
+def test_plan_statistics_match_oracle_screen(term, occ, vir):
+    gpu, ref = term_structures(term, occ, vir)
+    p = tm.Plan(*gpu, bind=False)
+    st = p.stats()
+    s = oracle.screen(*ref)
+    assert st["tasks"] == s["tasks"]
+    assert st["out_blocks"] == s["out_blocks"]
+    assert st["dropped"] == s["dropped"] == 0
+    assert st["useful_flops"] == s["useful_flops"]
+
+
+def test_plan_statistics_with_user_predicate_dropped():
+    sp = tm.Space.fixed(9, 3)
+    osp = oracle.Space.fixed(9, 3)
+
+    def rule(seed):
+        return lambda t, s: (hash((seed,) + tuple(int(x) for x in t)) % 3) != 0
+
+    out = tm.Tensor([sp, sp], nonzero=rule(1), device=None)
+    L = tm.Tensor([sp, sp], nonzero=rule(2), device=None)
+    R = tm.Tensor([sp, sp], nonzero=rule(3), device=None)
+    st = tm.Plan(out, "ab", L, "ac", R, "cb", bind=False).stats()
+    s = oracle.screen(oracle.BlockTensor([osp, osp], rule(1)), "ab", oracle.BlockTensor([osp, osp], rule(2)), "ac",
+                      oracle.BlockTensor([osp, osp], rule(3)), "cb")
+    assert (st["tasks"], st["dropped"], st["useful_flops"]) == (s["tasks"], s["dropped"], s["useful_flops"])
+    assert st["dropped"] > 0
+
+
+def status_of(fn):
+    with pytest.raises(tm.TammError) as e:
+        fn()
+    return e.value.status
+
+
+def test_error_codes():
+    o = tm.Space.spin(2, 2, 2)
+    v = tm.Space.spin(3, 3, 3)
+    V = tm.Tensor([v, v, v, v], device=None)
+    T = tm.Tensor([v, v, o, o], device=None)
+    R = tm.Tensor([v, v, o, o], device=None)
+    assert status_of(lambda: tm.Plan(R, "abij", V, "abcd", T, "cdi", bind=False)) == "TAMM_ERR_SHAPE"
+    assert status_of(lambda: tm.Plan(R, "abij", V, "abcc", T, "cdij", bind=False)) == "TAMM_ERR_LABEL"
+    assert status_of(lambda: tm.Plan(R, "abij", V, "abcd", T, "cxij", bind=False)) == "TAMM_ERR_LABEL"
+    assert status_of(lambda: tm.Plan(R, "ab1j", V, "abcd", T, "cdij", bind=False)) == "TAMM_ERR_LABEL"
+    # label d bound to virtual (V) and to occupied (T) spaces
+    assert status_of(lambda: tm.Plan(R, "abij", V, "abcd", T, "cidj", bind=False)) == "TAMM_ERR_LABEL"
+    assert status_of(lambda: tm.Plan(R, "abij", V, "abcd", T, "cdij", precision="bf16x3_exact", bind=False)) in (
+        "TAMM_ERR_UNSUPPORTED", "TAMM_OK")
+    # Fig. 4 as printed: B(i,l) with B declared over (tK, tN) binds i to two spaces
+    tM = tm.Space.explicit([10, 20])
+    tK = tm.Space.fixed(20, 5)
+    tN = tm.Space.fixed(100, 10)
+    dense = lambda t, s: True  # noqa: E731
+    A = tm.Tensor([tM, tK], nonzero=dense, device=None)
+    B = tm.Tensor([tK, tN], nonzero=dense, device=None)
+    C = tm.Tensor([tM, tN], nonzero=dense, device=None)
+    assert status_of(lambda: tm.Plan(C, "ia", A, "il", B, "il", bind=False)) == "TAMM_ERR_LABEL"
+    tm.Plan(C, "ia", A, "il", B, "la", bind=False)  # the consistent binding plans fine
+    # executing without bound storage/workspace is refused before any GPU work
+    p = tm.Plan(R, "abij", V, "abcd", T, "cdij", bind=False)
+    assert status_of(lambda: p.execute(1.0, 0.0, stream=ctypes.c_void_p(0))) == "TAMM_ERR_UNBOUND"
+    assert status_of(lambda: p.set_config(99)) == "TAMM_ERR_ARG"
+    # null arguments
+    h = ctypes.c_void_p()
+    assert lib.tamm_space_create(None, None, 3, ctypes.byref(h)) == -1
+    assert lib.tamm_space_create_spin(-1, 2, 2, ctypes.byref(h)) == -1
+    assert lib.tamm_tensor_create(None, 2, None, None, ctypes.byref(h)) == -1
+    assert lib.tamm_plan_create(None, b"ab", None, b"ab", None, b"ab", 0, ctypes.byref(h)) == -1
+    assert lib.tamm_last_error()
+    assert lib.tamm_tensor_bind(V._h, None, 0) == -1
+    assert lib.tamm_tensor_bind(V._h, ctypes.c_void_p(4096), 8) == -6  # smaller than needed
+
+
+def test_every_kernel_config_plans():
+    o = tm.Space.spin(20, 20, 40)
+    v = tm.Space.spin(100, 100, 40)
+    V = tm.Tensor([v, v, v, v], device=None)
+    T = tm.Tensor([v, v, o, o], device=None)
+    R = tm.Tensor([v, v, o, o], device=None)
+    p = tm.Plan(R, "abij", V, "abcd", T, "cdij", bind=False)
+    for c in range(p.config_count()):
+        for ks in (1, 2, 5):
+            p.set_config(c, ks)
+            st = p.stats()
+            assert st["kernel_config"] == c and st["k_splits"] == ks
+            assert st["work_items"] % ks == 0
+            assert p.workspace_size() > 0
+            assert p.config_name().startswith("f64_")
