@@ -185,8 +185,19 @@ int tamm_plan_stats_get(const tamm_plan* p, tamm_plan_stats* s);
  * and re-binding. */
 int tamm_plan_config_count(const tamm_plan* p, int32_t* count);
 int tamm_plan_set_config(tamm_plan* p, int32_t config, int32_t k_splits);
-/* Human-readable name of a configuration (static string), e.g. "f64_m128n64_k16". */
+/* Human-readable name of a configuration (static string), e.g. "f64_m128n64k16_w2x2". */
 const char* tamm_config_name(int32_t precision, int32_t config);
+
+/* Autotuner.  Measures every kernel configuration with K splits 1, 2, 4 and 8 that fits the
+ * given workspace (hipEvents on stream, `reps` timed executions after one warm-up; reps <= 0
+ * means 3), keeps the fastest, and leaves the plan configured and bound to `workspace`.  The
+ * trial executions run with alpha = 0, beta = 1, so out keeps its values when the operands are
+ * finite.  With a non-empty cache_path the result is appended to that text file keyed by the
+ * plan's structural signature, and a later call with the same structure reuses it without
+ * measuring.  tamm_plan_autotune_workspace_size gives the largest workspace any candidate needs.
+ * Synchronises the stream. */
+int tamm_plan_autotune_workspace_size(const tamm_plan* p, size_t* bytes);
+int tamm_plan_autotune(tamm_plan* p, void* workspace, size_t bytes, void* stream, const char* cache_path, int32_t reps);
 
 /* Enqueue the whole operation on stream: tamm_plan_screen then tamm_plan_contract.
  * Requires bound storage on all three tensors and a bound workspace. */
@@ -209,39 +220,60 @@ int tamm_plan_screen_result(tamm_plan* p, void* stream, int32_t* counts, int32_t
 int tamm_plan_destroy(tamm_plan* p);
 
 /* ------------------------------------------------------------------------------------------
- * Groups: many independent plans executed as one persistent launch (the single-GPU analogue
- * of running the operations of one scheduler level together, Sec. III-B).  Plans must be
- * bound to distinct output tensors (no two plans of a group write the same storage) and must
- * all use TAMM_PREC_F64.  Plans must outlive the group; the group uses its own workspace
- * (the plans' own workspaces are not needed for group execution).
+ * Groups: many independent plans executed together (the single-GPU analogue of running the
+ * operations of one scheduler level at once, Sec. III-B): one screening launch over every
+ * member, then one persistent contraction launch whose workgroups take output tiles of all
+ * members, heaviest first, from a shared counter.  Members must be float64 plans; no member may
+ * write storage that another member reads or writes (checked at execution, ERR_ARG).  Plans and
+ * their tensors must outlive the group; the group uses its own workspace (the members' own
+ * workspaces are not needed).  The group ignores the members' kernel configurations and runs
+ * without K splits.
  * ------------------------------------------------------------------------------------------ */
 int tamm_group_create(tamm_plan* const* plans, int32_t n, tamm_group** g);
 int tamm_group_workspace_size(const tamm_group* g, size_t* bytes);
+/* Bind caller-owned device workspace (256-byte aligned) and upload the members' static tables
+ * (synchronous).  Drops a captured graph. */
 int tamm_group_bind_workspace(tamm_group* g, void* dev_ptr, size_t bytes);
-/* Select the group's kernel configuration and persistent grid size (0 = one workgroup slot per
- * compute unit times the occupancy the configuration allows). */
+/* Select the kernel configuration (-1 = default) and the persistent grid size (0 = two
+ * workgroups per compute unit).  Requires re-querying the workspace size and re-binding. */
 int tamm_group_set_config(tamm_group* g, int32_t config, int32_t grid);
-/* alpha and beta are host arrays of n values, read during the call. */
+/* alpha and beta are host arrays of n values, read during the call.  If a graph was captured
+ * with the same alpha/beta and the members' storage bindings are unchanged, the graph is
+ * replayed; otherwise the kernels are launched directly (and any graph is dropped). */
 int tamm_group_execute(tamm_group* g, const double* alpha, const double* beta, void* stream);
+/* Capture the group's launches (counter reset, screening, persistent contraction; no memset or
+ * copy nodes) into a hipGraph on an internal stream, with alpha/beta fixed at these values;
+ * later tamm_group_execute calls with the same values replay it on their stream. */
+int tamm_group_capture(tamm_group* g, const double* alpha, const double* beta, void* stream);
+/* Autotuner for groups: every kernel configuration with persistent grids of 1, 2 and 4
+ * workgroups per compute unit, timed on stream with alpha = 0, beta = 1; keeps the fastest and
+ * caches it in cache_path (if non-empty) under the group's structural signature.  Needs a
+ * bound workspace large enough for the candidates (candidates that do not fit are skipped).
+ * Synchronises the stream. */
+int tamm_group_autotune(tamm_group* g, void* stream, const char* cache_path, int32_t reps);
+/* Active configuration, persistent grid (0 = automatic) and number of work items. */
+int tamm_group_stats(const tamm_group* g, int32_t* config, int32_t* grid, int64_t* work_items);
 int tamm_group_destroy(tamm_group* g);
 
 /* ------------------------------------------------------------------------------------------
  * Orbital-energy denominator update (the Jacobi step of CD-CCSD named in Sec. IV-B-1, which
- * turns a residual into amplitudes):
+ * turns a residual into amplitudes), prepared once and executed many times:
  *   out[p] = in[p] / D(p),  D(p) = sum of energy[d][p_d] over dims with sign[d] > 0, in
  *   dimension order, then minus energy[d][p_d] over dims with sign[d] < 0, in dimension order
  *   (for R[a,b,i,j] with signs (-,-,+,+): ((e_i + e_j) - e_a) - e_b).  IEEE float64 division
  *   (correctly rounded), over the stored blocks.
+ * out and in must have identical block structure and may be the same tensor; sign[d] in
+ * {-1, 0, +1} (read during create), at least one non-zero.  The workspace (caller-owned,
+ * 256-byte aligned) receives the block metadata at bind time (synchronous copy).
  * energy: host array of rank device pointers (read during the call), each indexing the full
- * untiled range of its dimension; a dimension with sign 0 takes no part and may pass NULL.
- * out and in must have identical block structure and may be the same tensor.  workspace:
- * caller-owned device memory of tamm_denominator_workspace_size bytes, 256-byte aligned; the
- * call enqueues the upload of the block metadata into it, so it must not be reused by another
- * call before this one's work on the stream has run.
+ * untiled range of its dimension; a dimension with sign 0 may pass NULL.
  * ------------------------------------------------------------------------------------------ */
-int tamm_denominator_workspace_size(const tamm_tensor* t, size_t* bytes);
-int tamm_denominator_update(tamm_tensor* out, const tamm_tensor* in, const double* const* energy, const int8_t* sign,
-                            void* workspace, size_t ws_bytes, void* stream);
+typedef struct tamm_denominator tamm_denominator;
+int tamm_denominator_create(tamm_tensor* out, const tamm_tensor* in, const int8_t* sign, tamm_denominator** d);
+int tamm_denominator_workspace_size(const tamm_denominator* d, size_t* bytes);
+int tamm_denominator_bind_workspace(tamm_denominator* d, void* workspace, size_t bytes);
+int tamm_denominator_execute(tamm_denominator* d, const double* const* energy, void* stream);
+int tamm_denominator_destroy(tamm_denominator* d);
 
 #ifdef __cplusplus
 }

@@ -8,6 +8,6 @@ thin Python binding; importing it does not load the native library, the first ca
 fails loudly if the library has not been built.
 """
 
-from .core import Denominator, Plan, Space, TammError, Tensor, contract  # noqa: F401
+from .core import Denominator, Group, Plan, Space, TammError, Tensor, contract  # noqa: F401
 
-__all__ = ["Space", "Tensor", "Plan", "contract", "Denominator", "TammError"]
+__all__ = ["Space", "Tensor", "Plan", "Group", "contract", "Denominator", "TammError"]

@@ -53,6 +53,8 @@ SIGNATURES = {
     "tamm_plan_config_count": (c_int, [c_vp, P(c_i32)]),
     "tamm_plan_set_config": (c_int, [c_vp, c_i32, c_i32]),
     "tamm_config_name": (c_char_p, [c_i32, c_i32]),
+    "tamm_plan_autotune_workspace_size": (c_int, [c_vp, P(c_size_t)]),
+    "tamm_plan_autotune": (c_int, [c_vp, c_vp, c_size_t, c_vp, c_char_p, c_i32]),
     "tamm_plan_execute": (c_int, [c_vp, c_dbl, c_dbl, c_vp]),
     "tamm_plan_screen": (c_int, [c_vp, c_vp]),
     "tamm_plan_contract": (c_int, [c_vp, c_dbl, c_dbl, c_vp]),
@@ -63,9 +65,15 @@ SIGNATURES = {
     "tamm_group_bind_workspace": (c_int, [c_vp, c_vp, c_size_t]),
     "tamm_group_set_config": (c_int, [c_vp, c_i32, c_i32]),
     "tamm_group_execute": (c_int, [c_vp, P(c_dbl), P(c_dbl), c_vp]),
+    "tamm_group_capture": (c_int, [c_vp, P(c_dbl), P(c_dbl), c_vp]),
+    "tamm_group_autotune": (c_int, [c_vp, c_vp, c_char_p, c_i32]),
+    "tamm_group_stats": (c_int, [c_vp, P(c_i32), P(c_i32), P(c_i64)]),
     "tamm_group_destroy": (c_int, [c_vp]),
+    "tamm_denominator_create": (c_int, [c_vp, c_vp, P(ctypes.c_int8), P(c_vp)]),
     "tamm_denominator_workspace_size": (c_int, [c_vp, P(c_size_t)]),
-    "tamm_denominator_update": (c_int, [c_vp, c_vp, P(c_vp), P(ctypes.c_int8), c_vp, c_size_t, c_vp]),
+    "tamm_denominator_bind_workspace": (c_int, [c_vp, c_vp, c_size_t]),
+    "tamm_denominator_execute": (c_int, [c_vp, P(c_vp), c_vp]),
+    "tamm_denominator_destroy": (c_int, [c_vp]),
 }
 
 STATUS = {
@@ -106,6 +114,12 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build the HIP library first (python -m paper_2201_01257_amd.build)")
+        # The library resolves libamdhip64.so.7 by soname.  torch ships its own HIP runtime under
+        # that soname; loading torch first makes both use that single runtime instead of two.
+        try:
+            import torch  # noqa: F401
+        except ImportError:  # pragma: no cover - C-only use without torch
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(lib, name)

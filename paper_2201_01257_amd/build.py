@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtamm_mi.so")
-SOURCES = ["tamm_mi.cpp", "kernels.hip", "kernels_mixed.hip", "group.hip"]
+SOURCES = ["capi_core.cpp", "plan.cpp", "denominator.cpp", "kernels.hip", "kernels_mixed.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",

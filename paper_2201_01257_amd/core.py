@@ -261,6 +261,15 @@ class Plan:
         if self.out.data is not None:
             self.bind_workspace()
 
+    def autotune(self, cache_path: str = "", reps: int = 3, stream=None):
+        """Measure the kernel configurations and keep the fastest (see tamm_plan_autotune)."""
+        n = ctypes.c_size_t()
+        check(load().tamm_plan_autotune_workspace_size(self._h, ctypes.byref(n)))
+        device = self.out.data.device
+        self._ws, ptr = _aligned_workspace(n.value, device)
+        s = current_stream_handle() if stream is None else stream
+        check(load().tamm_plan_autotune(self._h, ctypes.c_void_p(ptr), n.value, s, cache_path.encode(), reps))
+
     def config_name(self, config: Optional[int] = None) -> str:
         c = self.stats()["kernel_config"] if config is None else config
         return load().tamm_config_name(PRECISIONS[self.precision], c).decode()
@@ -322,18 +331,98 @@ class Denominator:
         torch = _torch()
         self.out, self.inp = out, inp
         self.energies = [None if e is None else e.to(dtype=torch.float64).contiguous() for e in energies]
-        self.signs = np.ascontiguousarray(np.asarray(signs, dtype=np.int8))
+        sg = np.ascontiguousarray(np.asarray(signs, dtype=np.int8))
+        h = ctypes.c_void_p()
+        check(load().tamm_denominator_create(out._h, inp._h, sg.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                                             ctypes.byref(h)))
+        self._h = h
         n = ctypes.c_size_t()
-        check(load().tamm_denominator_workspace_size(out._h, ctypes.byref(n)))
-        self.ws_bytes = max(n.value, 256)
-        self._ws, self._ws_ptr = _aligned_workspace(self.ws_bytes, out.data.device)
+        check(load().tamm_denominator_workspace_size(self._h, ctypes.byref(n)))
+        self.ws_bytes = n.value
+        self._ws, ptr = _aligned_workspace(self.ws_bytes, out.data.device)
+        check(load().tamm_denominator_bind_workspace(self._h, ctypes.c_void_p(ptr), self.ws_bytes))
         self._eptr = (ctypes.c_void_p * out.rank)(*[(0 if e is None else e.data_ptr()) for e in self.energies])
 
     def execute(self, stream=None):
         s = current_stream_handle() if stream is None else stream
-        check(load().tamm_denominator_update(self.out._h, self.inp._h, self._eptr,
-                                             self.signs.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
-                                             ctypes.c_void_p(self._ws_ptr), self.ws_bytes, s))
+        check(load().tamm_denominator_execute(self._h, self._eptr, s))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib._lib is not None:
+            _lib._lib.tamm_denominator_destroy(self._h)
+            self._h = None
 
 
-__all__ = ["Space", "Tensor", "Plan", "contract", "Denominator", "TammError", "PRECISIONS"]
+class Group:
+    """Independent float64 plans executed as one grouped persistent launch (optionally a hipGraph)."""
+
+    def __init__(self, plans: Sequence[Plan]):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        check(load().tamm_group_create(arr, len(self.plans), ctypes.byref(h)))
+        self._h = h
+        self._ws = None
+        self.device = self.plans[0].out.data.device if self.plans[0].out.data is not None else None
+        if self.device is not None:
+            self.bind_workspace()
+
+    def workspace_size(self) -> int:
+        n = ctypes.c_size_t()
+        check(load().tamm_group_workspace_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    def bind_workspace(self, nbytes: Optional[int] = None):
+        nbytes = self.workspace_size() if nbytes is None else nbytes
+        self._ws, ptr = _aligned_workspace(nbytes, self.device)
+        self._ws_bytes = nbytes
+        check(load().tamm_group_bind_workspace(self._h, ctypes.c_void_p(ptr), nbytes))
+
+    def set_config(self, config: int = -1, grid: int = 0):
+        check(load().tamm_group_set_config(self._h, config, grid))
+        if self.device is not None:
+            self.bind_workspace()
+
+    def stats(self) -> dict:
+        c, g, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        check(load().tamm_group_stats(self._h, ctypes.byref(c), ctypes.byref(g), ctypes.byref(n)))
+        return {"config": c.value, "grid": g.value, "work_items": n.value,
+                "config_name": load().tamm_config_name(0, c.value).decode()}
+
+    @staticmethod
+    def _arr(vals, n):
+        v = [float(x) for x in vals] if hasattr(vals, "__len__") else [float(vals)] * n
+        return (ctypes.c_double * n)(*v)
+
+    def execute(self, alpha, beta, stream=None):
+        n = len(self.plans)
+        s = current_stream_handle() if stream is None else stream
+        check(load().tamm_group_execute(self._h, self._arr(alpha, n), self._arr(beta, n), s))
+
+    def capture(self, alpha, beta, stream=None):
+        n = len(self.plans)
+        s = current_stream_handle() if stream is None else stream
+        check(load().tamm_group_capture(self._h, self._arr(alpha, n), self._arr(beta, n), s))
+
+    def autotune(self, cache_path: str = "", reps: int = 3, stream=None):
+        s = current_stream_handle() if stream is None else stream
+        # the largest workspace any candidate needs: try every configuration's size
+        best = self.workspace_size()
+        lib = load()
+        cur = self.stats()
+        cnt = ctypes.c_int32()
+        check(lib.tamm_plan_config_count(self.plans[0]._h, ctypes.byref(cnt)))
+        for c in range(cnt.value):
+            check(lib.tamm_group_set_config(self._h, c, 0))
+            best = max(best, self.workspace_size())
+        check(lib.tamm_group_set_config(self._h, cur["config"], cur["grid"]))
+        self.bind_workspace(best)
+        check(lib.tamm_group_autotune(self._h, s, cache_path.encode(), reps))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib._lib is not None:
+            _lib._lib.tamm_group_destroy(self._h)
+            self._h = None
+
+
+__all__ = ["Space", "Tensor", "Plan", "Group", "contract", "Denominator", "TammError", "PRECISIONS"]

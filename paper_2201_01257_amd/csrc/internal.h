@@ -12,15 +12,15 @@ constexpr int kMaxRank = 8;
 // it.  The flattened M (out&A) and N (out&B) extents and the offset tables that map a flattened
 // row/column to an element offset inside the block are fixed by the block's tile sizes.
 struct OutBlockDesc {
-  int64_t c_off;    // element offset of the block in out's storage
-  int32_t mext;     // flattened M extent (product of M-label tile sizes)
-  int32_t next;     // flattened N extent
-  int32_t c_tabM;   // start of out's M offset table (int32 pool)
-  int32_t c_tabN;   // start of out's N offset table
-  int32_t a_tbase;  // A-operand tile-linear index contributed by the M labels
-  int32_t b_tbase;  // B-operand tile-linear index contributed by the N labels
-  int32_t a_cbase;  // A-operand shape-class id contributed by the M labels
-  int32_t b_cbase;  // B-operand shape-class id contributed by the N labels
+  int64_t c_off;      // element offset of the block in out's storage
+  int32_t mext;       // flattened M extent (product of M-label tile sizes)
+  int32_t next;       // flattened N extent
+  int32_t c_tabM;     // start of out's M offset table (int32 pool)
+  int32_t c_tabN;     // start of out's N offset table
+  int32_t a_tbase;    // A-operand tile-linear index contributed by the M labels
+  int32_t b_tbase;    // B-operand tile-linear index contributed by the N labels
+  int32_t a_cbase;    // A-operand shape-class id contributed by the M labels
+  int32_t b_cbase;    // B-operand shape-class id contributed by the N labels
   int32_t pair_base;  // first slot of this block's surviving-pair list
   int32_t pad;
 };
@@ -41,13 +41,44 @@ static_assert(sizeof(PairDesc) == 40, "PairDesc layout");
 
 // One output macro-tile (or one K split of it) processed by one workgroup.
 struct WorkItem {
+  int32_t prob;   // problem index inside a group (0 for a single plan)
   int32_t ob;     // output block
   int32_t m0;     // first flattened row of the tile
   int32_t n0;     // first flattened column
   int32_t split;  // K split index (0 .. k_splits-1)
+  int32_t tile;   // index of the output tile inside its problem (partial-tile addressing)
+};
+static_assert(sizeof(WorkItem) == 24, "WorkItem layout");
+
+// Everything the contraction kernel needs about one contraction.
+struct ProblemDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  const OutBlockDesc* blocks;
+  const PairDesc* pairs;
+  const int32_t* counts;
+  const int32_t* pool;
+  double* partial;   // K-split partial tiles [tile][split][MT*NT], or null
+  double alpha;
+  double beta;
+  int32_t k_splits;
+  int32_t a_kc;      // 1: A's stride-1 label is summed (gather lanes run along k), 0: along m
+  int32_t b_kc;      // 1: B's stride-1 label is summed, 0: along n
+  int32_t pad;
+};
+static_assert(sizeof(ProblemDesc) == 96, "ProblemDesc layout");
+
+struct ContractParams {
+  ProblemDesc single;         // used when probs is null (one plan)
+  const ProblemDesc* probs;   // group: per-problem descriptors in device memory
+  const WorkItem* work;
+  int32_t* next_item;         // persistent launch: work counter (starts at gridDim.x), else null
+  int32_t n_work;
+  int32_t pad;
 };
 
-struct ScreenParams {
+struct ScreenDesc {
   const int64_t* a_tile_off;  // per A tile-linear index: element offset, -1 = not stored
   const int64_t* b_tile_off;
   const OutBlockDesc* blocks;
@@ -70,48 +101,44 @@ struct ScreenParams {
   int32_t b_cls_tabN;
 };
 
-struct ContractParams {
-  const double* A;
-  const double* B;
-  double* C;
-  const OutBlockDesc* blocks;
-  const PairDesc* pairs;
-  const int32_t* counts;
-  const int32_t* pool;
-  const WorkItem* work;
-  double* partial;     // K-split partial tiles (work item major), or null
-  int32_t n_work;
-  int32_t k_splits;
-  double alpha;
-  double beta;
+struct ScreenParams {
+  ScreenDesc single;
+  const ScreenDesc* probs;       // group: per-problem screen descriptors
+  const int32_t* item_prob;      // group: problem of each screening item
+  const int32_t* item_block;     // group: output block of each screening item
+  int32_t n_items;               // single: = single.n_blocks
+  int32_t pad;
+};
+
+struct ReduceItem {
+  int32_t prob, ob, m0, n0, tile, pad;
 };
 
 struct ReduceParams {
-  double* C;
-  const OutBlockDesc* blocks;
-  const int32_t* pool;
-  const WorkItem* work;   // all work items; the k_splits items of a tile are adjacent
-  const double* partial;
-  int32_t n_tiles;
-  int32_t k_splits;
+  ProblemDesc single;
+  const ProblemDesc* probs;
+  const ReduceItem* items;
+  int32_t n_items;
   int32_t tile_m;
   int32_t tile_n;
-  double alpha;
-  double beta;
+  int32_t pad;
 };
 
 struct DenomParams {
   double* out;
   const double* in;
-  const int64_t* block_off;   // per stored block: element offset
-  const int32_t* block_tiles; // per stored block: rank tile indices
-  const int64_t* tile_offset; // per dim: untiled start of each tile (concatenated, dim starts below)
+  const int64_t* block_off;    // per stored block: element offset
+  const int32_t* block_tiles;  // per stored block: rank tile indices
+  const int64_t* tile_offset;  // per dim: untiled start of each tile (concatenated)
   const int64_t* tile_size;
-  int32_t dim_tile_base[kMaxRank];
   const double* energy[kMaxRank];
+  int32_t dim_tile_base[kMaxRank];
   int8_t sign[kMaxRank];
   int32_t rank;
-  int64_t n_blocks;
+  int32_t chunk;                // elements per workgroup
+  const int32_t* item_block;    // per workgroup: block index
+  const int32_t* item_start;    // per workgroup: first element inside the block
+  int64_t n_items;              // workgroups
 };
 
 // Kernel configuration of the FP64 contraction kernel family.
@@ -123,10 +150,11 @@ struct F64Config {
 int f64_config_count();
 const F64Config& f64_config(int id);
 
-// Launchers (kernels.hip).  Return hipError_t of the launch.
+// Launchers (kernels.hip).  Return hipError_t of the launch.  grid <= 0: one workgroup per item.
 hipError_t launch_screen(const ScreenParams& p, hipStream_t s);
-hipError_t launch_contract_f64(int config, bool a_kcontig, bool b_kcontig, const ContractParams& p, hipStream_t s);
+hipError_t launch_contract_f64(int config, int layout, const ContractParams& p, int grid, hipStream_t s);
 hipError_t launch_reduce(const ReduceParams& p, hipStream_t s);
-hipError_t launch_denominator(const DenomParams& p, int64_t max_block_elems, hipStream_t s);
+hipError_t launch_set_counter(int32_t* counter, int32_t value, hipStream_t s);
+hipError_t launch_denominator(const DenomParams& p, hipStream_t s);
 
 }  // namespace tamm

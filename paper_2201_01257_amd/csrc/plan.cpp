@@ -1,0 +1,1150 @@
+// Host side of the C ABI, part 2: contraction plans (label analysis, offset tables, screening
+// setup, work decomposition), grouped persistent execution with hipGraph replay, and the
+// autotuner that picks kernel configurations by measurement.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "host.h"
+
+using namespace tamm;
+
+namespace {
+
+struct Label {
+  char c;
+  int od = -1, ad = -1, bd = -1;  // dimension in out, A, B (-1 if absent)
+  std::shared_ptr<SpaceData> sp;
+  std::vector<int32_t> cls;       // size class per tile
+  std::vector<int64_t> cls_size;  // tile size of each class
+};
+
+int32_t pool_push(std::vector<int32_t>& pool, const std::vector<int64_t>& v) {
+  int32_t start = (int32_t)pool.size();
+  for (int64_t x : v) pool.push_back((int32_t)x);
+  return start;
+}
+
+// Offset table of one label group inside blocks of one operand shape: flattened index (mixed
+// radix over `group`, last fastest) -> element offset in the row-major block.
+std::vector<int64_t> group_table(const std::vector<int>& group, const std::vector<int64_t>& lab_ext,
+                                 const std::vector<int64_t>& lab_stride) {
+  int64_t n = 1;
+  for (int l : group) n *= lab_ext[l];
+  std::vector<int64_t> tab(n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t rem = i, off = 0;
+    for (int q = (int)group.size() - 1; q >= 0; --q) {
+      const int l = group[q];
+      off += (rem % lab_ext[l]) * lab_stride[l];
+      rem /= lab_ext[l];
+    }
+    tab[i] = off;
+  }
+  return tab;
+}
+
+uint64_t fnv(uint64_t h, const void* data, size_t n) {
+  const unsigned char* p = (const unsigned char*)data;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 0x100000001B3ULL;
+  }
+  return h;
+}
+
+// Device regions of one contraction's static tables and screened pair lists, relative to a base.
+struct Layout {
+  size_t pool = 0, atile = 0, btile = 0, blocks = 0, pairs = 0, counts = 0, end = 0;
+};
+
+}  // namespace
+
+struct tamm_plan {
+  tamm_tensor* out = nullptr;
+  const tamm_tensor* lhs = nullptr;
+  const tamm_tensor* rhs = nullptr;
+  const tamm_tensor* A = nullptr;  // the operand whose labels are M + K
+  const tamm_tensor* B = nullptr;
+  bool swapped = false;
+  tamm_precision prec = TAMM_PREC_F64;
+  std::vector<Label> labels;
+  std::vector<int> M, N, K;        // label indices in flattening order (last fastest)
+  std::vector<int> k_lhs_order;    // for each K label in lhs order: its position in K
+  bool a_kc = true, b_kc = true;
+  std::vector<int32_t> pool;
+  ScreenDesc sd{};                 // device pointers filled when bound
+  int64_t n_kt = 1;
+  std::vector<OutBlockDesc> blocks;
+  std::vector<double> block_cost;  // sum of K extents of the surviving pairs of each block
+  uint64_t signature = 0;
+  // kernel configuration and work decomposition
+  int config = -1;
+  int k_splits = 1;
+  std::vector<WorkItem> work;
+  std::vector<ReduceItem> reduce;
+  tamm_plan_stats stats{};
+  // workspace: static layout, then work list, reduce list, partial tiles
+  Layout lay;
+  size_t off_work = 0, off_reduce = 0, off_partial = 0, ws_size = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_bound = false;
+  bool screened = false;
+  bool executed = false;
+};
+
+static int configure_work(tamm_plan* p, int config, int k_splits);
+
+static Layout make_layout(const tamm_plan* p, size_t base) {
+  Layout L;
+  size_t off = align256(base);
+  L.pool = off;
+  off = align256(off + p->pool.size() * sizeof(int32_t));
+  L.atile = off;
+  off = align256(off + p->A->tile_off.size() * sizeof(int64_t));
+  L.btile = off;
+  off = align256(off + p->B->tile_off.size() * sizeof(int64_t));
+  L.blocks = off;
+  off = align256(off + p->blocks.size() * sizeof(OutBlockDesc));
+  L.pairs = off;
+  off = align256(off + p->blocks.size() * (size_t)p->n_kt * sizeof(PairDesc));
+  L.counts = off;
+  off = align256(off + p->blocks.size() * sizeof(int32_t));
+  L.end = off;
+  return L;
+}
+
+static int upload_static(const tamm_plan* p, char* ws, const Layout& L) {
+  HIP_TRY(hipMemcpy(ws + L.pool, p->pool.data(), p->pool.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ws + L.atile, p->A->tile_off.data(), p->A->tile_off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ws + L.btile, p->B->tile_off.data(), p->B->tile_off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  if (!p->blocks.empty())
+    HIP_TRY(hipMemcpy(ws + L.blocks, p->blocks.data(), p->blocks.size() * sizeof(OutBlockDesc), hipMemcpyHostToDevice));
+  return TAMM_OK;
+}
+
+static ScreenDesc screen_desc(const tamm_plan* p, char* ws, const Layout& L) {
+  ScreenDesc s = p->sd;
+  s.a_tile_off = (const int64_t*)(ws + L.atile);
+  s.b_tile_off = (const int64_t*)(ws + L.btile);
+  s.blocks = (const OutBlockDesc*)(ws + L.blocks);
+  s.pairs = (PairDesc*)(ws + L.pairs);
+  s.counts = (int32_t*)(ws + L.counts);
+  s.pool = (const int32_t*)(ws + L.pool);
+  s.n_blocks = (int32_t)p->blocks.size();
+  return s;
+}
+
+static ProblemDesc problem_desc(const tamm_plan* p, char* ws, const Layout& L, double* partial, int k_splits, double alpha,
+                                double beta) {
+  ProblemDesc d{};
+  d.A = p->A->dev;
+  d.B = p->B->dev;
+  d.C = p->out->dev;
+  d.blocks = (const OutBlockDesc*)(ws + L.blocks);
+  d.pairs = (const PairDesc*)(ws + L.pairs);
+  d.counts = (const int32_t*)(ws + L.counts);
+  d.pool = (const int32_t*)(ws + L.pool);
+  d.partial = partial;
+  d.alpha = alpha;
+  d.beta = beta;
+  d.k_splits = k_splits;
+  d.a_kc = p->a_kc ? 1 : 0;
+  d.b_kc = p->b_kc ? 1 : 0;
+  return d;
+}
+
+extern "C" int tamm_plan_create(tamm_tensor* out, const char* out_lbl, const tamm_tensor* lhs, const char* lhs_lbl,
+                                const tamm_tensor* rhs, const char* rhs_lbl, tamm_precision precision, tamm_plan** plan) {
+  if (!plan) return fail(TAMM_ERR_ARG, "null output pointer");
+  *plan = nullptr;
+  if (!out || !lhs || !rhs || !out_lbl || !lhs_lbl || !rhs_lbl) return fail(TAMM_ERR_ARG, "null tensor or label string");
+  if (precision != TAMM_PREC_F64)
+    return fail(TAMM_ERR_UNSUPPORTED, "precision %d is not available in this build", (int)precision);
+  const tamm_tensor* ts[3] = {out, lhs, rhs};
+  const char* ls[3] = {out_lbl, lhs_lbl, rhs_lbl};
+  for (int x = 0; x < 3; ++x) {
+    const size_t n = strlen(ls[x]);
+    if ((int)n != ts[x]->rank)
+      return fail(TAMM_ERR_SHAPE, "label string '%s' has %zu letters for a rank-%d tensor", ls[x], n, ts[x]->rank);
+    for (size_t i = 0; i < n; ++i) {
+      const char c = ls[x][i];
+      if (!((c >= 'a' && c <= 'z') || (c >= 'A' && c <= 'Z'))) return fail(TAMM_ERR_LABEL, "label '%c' is not a letter", c);
+      for (size_t j = 0; j < i; ++j)
+        if (ls[x][j] == c) return fail(TAMM_ERR_LABEL, "label '%c' repeats inside '%s'", c, ls[x]);
+    }
+  }
+  auto p = std::make_unique<tamm_plan>();
+  p->out = out;
+  p->lhs = lhs;
+  p->rhs = rhs;
+  p->prec = precision;
+  // orientation: the operand holding out's last label becomes B, so output stores run along N
+  const char last = out_lbl[out->rank - 1];
+  p->swapped = strchr(lhs_lbl, last) != nullptr;
+  p->A = p->swapped ? rhs : lhs;
+  p->B = p->swapped ? lhs : rhs;
+  const char* a_lbl = p->swapped ? rhs_lbl : lhs_lbl;
+  const char* b_lbl = p->swapped ? lhs_lbl : rhs_lbl;
+  std::map<char, int> idx;
+  auto touch = [&](char c) -> Label& {
+    auto it = idx.find(c);
+    if (it == idx.end()) {
+      idx[c] = (int)p->labels.size();
+      p->labels.push_back(Label{c});
+      return p->labels.back();
+    }
+    return p->labels[it->second];
+  };
+  for (int d = 0; d < out->rank; ++d) touch(out_lbl[d]).od = d;
+  for (int d = 0; d < p->A->rank; ++d) touch(a_lbl[d]).ad = d;
+  for (int d = 0; d < p->B->rank; ++d) touch(b_lbl[d]).bd = d;
+  for (auto& L : p->labels) {
+    const int n = (L.od >= 0) + (L.ad >= 0) + (L.bd >= 0);
+    if (n != 2) return fail(TAMM_ERR_LABEL, "label '%c' appears in %d tensors; each label must appear in exactly two", L.c, n);
+    std::shared_ptr<SpaceData> s[3] = {L.od >= 0 ? out->dims[L.od] : nullptr, L.ad >= 0 ? p->A->dims[L.ad] : nullptr,
+                                       L.bd >= 0 ? p->B->dims[L.bd] : nullptr};
+    for (int x = 0; x < 3; ++x)
+      if (s[x]) {
+        if (!L.sp) L.sp = s[x];
+        else if (!L.sp->same(*s[x])) return fail(TAMM_ERR_LABEL, "label '%c' binds two different tiled spaces", L.c);
+      }
+    for (int t = 0; t < L.sp->ntiles(); ++t) {
+      auto it = std::find(L.cls_size.begin(), L.cls_size.end(), L.sp->size[t]);
+      if (it == L.cls_size.end()) {
+        L.cls.push_back((int32_t)L.cls_size.size());
+        L.cls_size.push_back(L.sp->size[t]);
+      } else {
+        L.cls.push_back((int32_t)(it - L.cls_size.begin()));
+      }
+    }
+  }
+  const int nl = (int)p->labels.size();
+  // flattening orders: M and N follow the operand's own dimension order; K follows the operand
+  // whose stride-1 label is a K label (A first), so that gathers run along memory.
+  std::vector<int> a_dim_label(p->A->rank), b_dim_label(p->B->rank), o_dim_label(out->rank);
+  for (int l = 0; l < nl; ++l) {
+    if (p->labels[l].ad >= 0) a_dim_label[p->labels[l].ad] = l;
+    if (p->labels[l].bd >= 0) b_dim_label[p->labels[l].bd] = l;
+    if (p->labels[l].od >= 0) o_dim_label[p->labels[l].od] = l;
+  }
+  for (int d = 0; d < p->A->rank; ++d)
+    if (p->labels[a_dim_label[d]].od >= 0) p->M.push_back(a_dim_label[d]);
+  for (int d = 0; d < p->B->rank; ++d)
+    if (p->labels[b_dim_label[d]].od >= 0) p->N.push_back(b_dim_label[d]);
+  const int a_last = a_dim_label[p->A->rank - 1], b_last = b_dim_label[p->B->rank - 1];
+  p->a_kc = p->labels[a_last].od < 0;
+  p->b_kc = p->labels[b_last].od < 0;
+  if (p->a_kc || !p->b_kc) {
+    for (int d = 0; d < p->A->rank; ++d)
+      if (p->labels[a_dim_label[d]].od < 0) p->K.push_back(a_dim_label[d]);
+  } else {
+    for (int d = 0; d < p->B->rank; ++d)
+      if (p->labels[b_dim_label[d]].od < 0) p->K.push_back(b_dim_label[d]);
+  }
+  if (p->K.size() > (size_t)kMaxRank) return fail(TAMM_ERR_UNSUPPORTED, "too many contracted labels");
+  for (int i = 0; lhs_lbl[i]; ++i) {
+    const int l = idx[lhs_lbl[i]];
+    if (p->labels[l].od < 0) p->k_lhs_order.push_back((int)(std::find(p->K.begin(), p->K.end(), l) - p->K.begin()));
+  }
+
+  // ---- offset tables per operand shape class ------------------------------------------------
+  auto& pool = p->pool;
+  struct OpInfo {
+    const tamm_tensor* t;
+    std::vector<int> dim_label;
+    std::vector<int64_t> cstride;  // class-id stride per dim
+    int64_t ncls = 1;
+  };
+  auto op_info = [&](const tamm_tensor* t, const std::vector<int>& dl) {
+    OpInfo o{t, dl, std::vector<int64_t>(t->rank, 1), 1};
+    for (int d = t->rank - 1; d >= 0; --d) {
+      o.cstride[d] = o.ncls;
+      o.ncls *= (int64_t)p->labels[dl[d]].cls_size.size();
+    }
+    return o;
+  };
+  OpInfo ai = op_info(p->A, a_dim_label), bi = op_info(p->B, b_dim_label), oi = op_info(out, o_dim_label);
+  if (ai.ncls + bi.ncls + oi.ncls > 100000) return fail(TAMM_ERR_UNSUPPORTED, "too many distinct block shapes");
+  auto build_tables = [&](const OpInfo& o, const std::vector<int>& g1, const std::vector<int>& g2,
+                          std::vector<int64_t>& start1, std::vector<int64_t>& start2) {
+    start1.assign(o.ncls, 0);
+    start2.assign(o.ncls, 0);
+    std::vector<int64_t> lab_ext(nl, 1), lab_stride(nl, 0);
+    for (int64_t c = 0; c < o.ncls; ++c) {
+      int64_t stride = 1;
+      for (int d = o.t->rank - 1; d >= 0; --d) {
+        const Label& L = p->labels[o.dim_label[d]];
+        const int64_t cl = (c / o.cstride[d]) % (int64_t)L.cls_size.size();
+        lab_ext[o.dim_label[d]] = L.cls_size[cl];
+        lab_stride[o.dim_label[d]] = stride;
+        stride *= L.cls_size[cl];
+      }
+      if (stride > INT32_MAX) return false;
+      start1[c] = pool_push(pool, group_table(g1, lab_ext, lab_stride));
+      start2[c] = pool_push(pool, group_table(g2, lab_ext, lab_stride));
+      if (pool.size() > (size_t)INT32_MAX / 2) return false;
+    }
+    return true;
+  };
+  std::vector<int64_t> aM, aK, bK, bN, oM, oN;
+  if (!build_tables(ai, p->M, p->K, aM, aK) || !build_tables(bi, p->K, p->N, bK, bN) || !build_tables(oi, p->M, p->N, oM, oN))
+    return fail(TAMM_ERR_UNSUPPORTED, "a block has more than 2^31 elements or the offset tables are too large");
+  ScreenDesc& sd = p->sd;
+  memset(&sd, 0, sizeof(sd));
+  sd.a_cls_tabM = pool_push(pool, aM);
+  sd.a_cls_tabK = pool_push(pool, aK);
+  sd.b_cls_tabK = pool_push(pool, bK);
+  sd.b_cls_tabN = pool_push(pool, bN);
+  sd.nk = (int)p->K.size();
+  p->n_kt = 1;
+  for (int q = 0; q < sd.nk; ++q) {
+    const Label& L = p->labels[p->K[q]];
+    sd.k_ntiles[q] = L.sp->ntiles();
+    p->n_kt *= L.sp->ntiles();
+    sd.a_tstride[q] = (int32_t)p->A->tstride[L.ad];
+    sd.b_tstride[q] = (int32_t)p->B->tstride[L.bd];
+    sd.a_cstride[q] = (int32_t)ai.cstride[L.ad];
+    sd.b_cstride[q] = (int32_t)bi.cstride[L.bd];
+    sd.k_size_tab[q] = pool_push(pool, L.sp->size);
+    std::vector<int64_t> cls(L.cls.begin(), L.cls.end());
+    sd.k_cls_tab[q] = pool_push(pool, cls);
+  }
+  if (p->n_kt > (1 << 20)) return fail(TAMM_ERR_UNSUPPORTED, "too many contracted tile tuples");
+  sd.n_kt = (int32_t)p->n_kt;
+
+  // ---- output blocks and host structural screening statistics ------------------------------
+  const int64_t nob = (int64_t)out->block_off.size();
+  if (nob * p->n_kt > (int64_t)1 << 28) return fail(TAMM_ERR_UNSUPPORTED, "pair capacity too large");
+  p->blocks.resize(nob);
+  p->block_cost.assign(nob, 0.0);
+  double flops = 0;
+  int64_t tasks = 0;
+  for (int64_t b = 0; b < nob; ++b) {
+    const int32_t* ot = &out->block_tiles[b * out->rank];
+    OutBlockDesc& d = p->blocks[b];
+    memset(&d, 0, sizeof(d));
+    d.c_off = out->block_off[b];
+    int64_t mext = 1, next = 1, ocls = 0;
+    for (int l : p->M) mext *= p->labels[l].sp->size[ot[p->labels[l].od]];
+    for (int l : p->N) next *= p->labels[l].sp->size[ot[p->labels[l].od]];
+    for (int dd = 0; dd < out->rank; ++dd) ocls += p->labels[o_dim_label[dd]].cls[ot[dd]] * oi.cstride[dd];
+    d.mext = (int32_t)mext;
+    d.next = (int32_t)next;
+    d.c_tabM = (int32_t)oM[ocls];
+    d.c_tabN = (int32_t)oN[ocls];
+    int64_t atb = 0, btb = 0, acb = 0, bcb = 0;
+    for (int l : p->M) {
+      const Label& L = p->labels[l];
+      atb += ot[L.od] * p->A->tstride[L.ad];
+      acb += L.cls[ot[L.od]] * ai.cstride[L.ad];
+    }
+    for (int l : p->N) {
+      const Label& L = p->labels[l];
+      btb += ot[L.od] * p->B->tstride[L.bd];
+      bcb += L.cls[ot[L.od]] * bi.cstride[L.bd];
+    }
+    d.a_tbase = (int32_t)atb;
+    d.b_tbase = (int32_t)btb;
+    d.a_cbase = (int32_t)acb;
+    d.b_cbase = (int32_t)bcb;
+    d.pair_base = (int32_t)(b * p->n_kt);
+    // host count of surviving pairs (statistics and scheduling cost; the kernels use the pair
+    // list produced by the GPU screen)
+    for (int64_t kt = 0; kt < p->n_kt; ++kt) {
+      int64_t rem = kt, alin = atb, blin = btb, kext = 1;
+      for (int q = sd.nk - 1; q >= 0; --q) {
+        const int t = (int)(rem % sd.k_ntiles[q]);
+        rem /= sd.k_ntiles[q];
+        alin += (int64_t)t * sd.a_tstride[q];
+        blin += (int64_t)t * sd.b_tstride[q];
+        kext *= p->labels[p->K[q]].sp->size[t];
+      }
+      if (p->A->tile_off[alin] >= 0 && p->B->tile_off[blin] >= 0) {
+        ++tasks;
+        flops += 2.0 * (double)mext * (double)next * (double)kext;
+        p->block_cost[b] += (double)kext;
+      }
+    }
+  }
+  // dropped pairs: surviving pairs whose output block is not stored (user predicates only)
+  int64_t dropped = 0;
+  {
+    std::vector<int32_t> ot(out->rank);
+    const int64_t ntup = (int64_t)out->tile_off.size();
+    for (int64_t lin = 0; lin < ntup; ++lin) {
+      if (out->tile_off[lin] >= 0) continue;
+      int64_t rem = lin;
+      for (int dd = out->rank - 1; dd >= 0; --dd) {
+        ot[dd] = (int32_t)(rem % out->dims[dd]->ntiles());
+        rem /= out->dims[dd]->ntiles();
+      }
+      int64_t atb = 0, btb = 0;
+      for (int l : p->M) atb += ot[p->labels[l].od] * p->A->tstride[p->labels[l].ad];
+      for (int l : p->N) btb += ot[p->labels[l].od] * p->B->tstride[p->labels[l].bd];
+      for (int64_t kt = 0; kt < p->n_kt; ++kt) {
+        int64_t r2 = kt, alin = atb, blin = btb;
+        for (int q = sd.nk - 1; q >= 0; --q) {
+          const int t = (int)(r2 % sd.k_ntiles[q]);
+          r2 /= sd.k_ntiles[q];
+          alin += (int64_t)t * sd.a_tstride[q];
+          blin += (int64_t)t * sd.b_tstride[q];
+        }
+        if (p->A->tile_off[alin] >= 0 && p->B->tile_off[blin] >= 0) ++dropped;
+      }
+    }
+  }
+  tamm_plan_stats& st = p->stats;
+  st.out_blocks = nob;
+  st.candidates = nob * p->n_kt;
+  st.tasks = tasks;
+  st.dropped = dropped;
+  st.useful_flops = flops;
+  st.algorithmic_bytes = 8.0 * ((double)lhs->numel + (double)rhs->numel + 2.0 * (double)out->numel);
+  // structural signature (autotuner cache key)
+  uint64_t h = 0xCBF29CE484222325ULL;
+  const int32_t hdr[6] = {(int32_t)p->M.size(), (int32_t)p->N.size(), (int32_t)p->K.size(), (int32_t)p->a_kc,
+                          (int32_t)p->b_kc, (int32_t)precision};
+  h = fnv(h, hdr, sizeof(hdr));
+  for (int l : p->M) h = fnv(h, p->labels[l].sp->size.data(), p->labels[l].sp->size.size() * 8);
+  for (int l : p->N) h = fnv(h, p->labels[l].sp->size.data(), p->labels[l].sp->size.size() * 8);
+  for (int l : p->K) h = fnv(h, p->labels[l].sp->size.data(), p->labels[l].sp->size.size() * 8);
+  h = fnv(h, &tasks, sizeof(tasks));
+  h = fnv(h, &nob, sizeof(nob));
+  h = fnv(h, p->block_cost.data(), p->block_cost.size() * sizeof(double));
+  p->signature = h;
+  int rc = configure_work(p.get(), -1, 0);
+  if (rc != TAMM_OK) return rc;
+  *plan = p.release();
+  return ok();
+}
+
+// Number of output tiles and padding factor of one configuration.
+static std::pair<int64_t, double> tiles_for(const tamm_plan* p, int c) {
+  const F64Config& f = f64_config(c);
+  int64_t n = 0;
+  double area = 0, useful = 0;
+  for (const auto& b : p->blocks) {
+    const int64_t tm = (b.mext + f.mt - 1) / f.mt, tn = (b.next + f.nt - 1) / f.nt;
+    n += tm * tn;
+    area += (double)tm * f.mt * tn * f.nt;
+    useful += (double)b.mext * b.next;
+  }
+  return std::make_pair(n, useful > 0 ? area / useful : 1.0);
+}
+
+// Default configuration when the autotuner has not run: the largest tile that gives every compute
+// unit two tiles with little padding.
+static int default_config(const tamm_plan* p) {
+  int best = 0;
+  double best_score = -1;
+  for (int c = 0; c < f64_config_count(); ++c) {
+    auto tw = tiles_for(p, c);
+    const F64Config& f = f64_config(c);
+    if (f.kt != 16 || f.wgm * f.wgn != 4 || f.mt > 128 || f.nt > 128) continue;
+    double score = (double)f.mt * f.nt / tw.second;
+    if (tw.first < 512) score *= (double)tw.first / 512.0;
+    if (score > best_score) {
+      best_score = score;
+      best = c;
+    }
+  }
+  return best;
+}
+
+// Work decomposition for one kernel configuration: macro-tiles of every stored output block,
+// heaviest first (longest-processing-time order), with the K splits of a tile adjacent.
+static int configure_work(tamm_plan* p, int config, int k_splits) {
+  const int ncfg = f64_config_count();
+  const int64_t nob = (int64_t)p->blocks.size();
+  if (config < 0) config = default_config(p);
+  if (config >= ncfg) return fail(TAMM_ERR_ARG, "kernel configuration %d does not exist (%d available)", config, ncfg);
+  const F64Config& f = f64_config(config);
+  const int64_t ntiles = tiles_for(p, config).first;
+  if (k_splits <= 0) {
+    k_splits = 1;
+    // output-starved operations: split K so that there are about two tiles per compute unit
+    if (ntiles > 0 && ntiles < 512) {
+      double maxk = 0;
+      for (double c : p->block_cost) maxk = std::max(maxk, c);
+      const int want = (int)((512 + ntiles - 1) / ntiles);
+      const int kmax = (int)std::max(1.0, maxk / (4.0 * f.kt));
+      k_splits = std::max(1, std::min({want, 16, kmax}));
+    }
+  }
+  if (k_splits > 64) return fail(TAMM_ERR_ARG, "k_splits must be in [1, 64]");
+  struct Tile {
+    double cost;
+    int32_t ob, m0, n0;
+  };
+  std::vector<Tile> tiles;
+  tiles.reserve(ntiles);
+  for (int64_t b = 0; b < nob; ++b) {
+    const auto& d = p->blocks[b];
+    for (int32_t m0 = 0; m0 < d.mext; m0 += f.mt)
+      for (int32_t n0 = 0; n0 < d.next; n0 += f.nt)
+        tiles.push_back(Tile{p->block_cost[b] * std::min(f.mt, d.mext - m0) * std::min(f.nt, d.next - n0), (int32_t)b, m0, n0});
+  }
+  std::stable_sort(tiles.begin(), tiles.end(), [](const Tile& x, const Tile& y) { return x.cost > y.cost; });
+  p->work.clear();
+  p->reduce.clear();
+  for (size_t t = 0; t < tiles.size(); ++t) {
+    for (int s = 0; s < k_splits; ++s)
+      p->work.push_back(WorkItem{0, tiles[t].ob, tiles[t].m0, tiles[t].n0, s, (int32_t)t});
+    if (k_splits > 1) p->reduce.push_back(ReduceItem{0, tiles[t].ob, tiles[t].m0, tiles[t].n0, (int32_t)t, 0});
+  }
+  if (p->work.size() > (size_t)INT32_MAX / 2) return fail(TAMM_ERR_UNSUPPORTED, "too many work items");
+  p->config = config;
+  p->k_splits = k_splits;
+  p->stats.work_items = (int64_t)p->work.size();
+  p->stats.kernel_config = config;
+  p->stats.k_splits = k_splits;
+  p->lay = make_layout(p, 0);
+  size_t off = p->lay.end;
+  p->off_work = off;
+  off = align256(off + p->work.size() * sizeof(WorkItem));
+  p->off_reduce = off;
+  off = align256(off + p->reduce.size() * sizeof(ReduceItem));
+  p->off_partial = off;
+  if (k_splits > 1) off = align256(off + tiles.size() * (size_t)k_splits * f.mt * f.nt * sizeof(double));
+  p->ws_size = std::max<size_t>(off, 256);
+  p->ws_bound = false;
+  p->screened = false;
+  p->executed = false;
+  return TAMM_OK;
+}
+
+extern "C" int tamm_plan_workspace_size(const tamm_plan* p, size_t* bytes) {
+  if (!p || !bytes) return fail(TAMM_ERR_ARG, "null argument");
+  *bytes = p->ws_size;
+  return ok();
+}
+
+static int bind_plan(tamm_plan* p, void* dev_ptr, size_t bytes) {
+  if (!dev_ptr || ((uintptr_t)dev_ptr) % 256) return fail(TAMM_ERR_WORKSPACE, "workspace must be non-null and 256-byte aligned");
+  if (bytes < p->ws_size) return fail(TAMM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", bytes, p->ws_size);
+  char* ws = (char*)dev_ptr;
+  int rc = upload_static(p, ws, p->lay);
+  if (rc != TAMM_OK) return rc;
+  if (!p->work.empty()) HIP_TRY(hipMemcpy(ws + p->off_work, p->work.data(), p->work.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+  if (!p->reduce.empty())
+    HIP_TRY(hipMemcpy(ws + p->off_reduce, p->reduce.data(), p->reduce.size() * sizeof(ReduceItem), hipMemcpyHostToDevice));
+  p->ws = ws;
+  p->ws_bytes = bytes;
+  p->ws_bound = true;
+  p->screened = false;
+  p->executed = false;
+  return TAMM_OK;
+}
+
+extern "C" int tamm_plan_bind_workspace(tamm_plan* p, void* dev_ptr, size_t bytes) {
+  if (!p) return fail(TAMM_ERR_ARG, "null plan");
+  const int rc = bind_plan(p, dev_ptr, bytes);
+  return rc == TAMM_OK ? ok() : rc;
+}
+
+extern "C" int tamm_plan_stats_get(const tamm_plan* p, tamm_plan_stats* s) {
+  if (!p || !s) return fail(TAMM_ERR_ARG, "null argument");
+  *s = p->stats;
+  return ok();
+}
+
+extern "C" int tamm_plan_config_count(const tamm_plan* p, int32_t* count) {
+  if (!p || !count) return fail(TAMM_ERR_ARG, "null argument");
+  *count = f64_config_count();
+  return ok();
+}
+
+extern "C" int tamm_plan_set_config(tamm_plan* p, int32_t config, int32_t k_splits) {
+  if (!p) return fail(TAMM_ERR_ARG, "null plan");
+  if (config < 0 || config >= f64_config_count()) return fail(TAMM_ERR_ARG, "configuration %d does not exist", config);
+  if (k_splits < 0 || k_splits > 64) return fail(TAMM_ERR_ARG, "k_splits must be in [0, 64]");
+  const int rc = configure_work(p, config, k_splits);
+  if (rc != TAMM_OK) return rc;
+  return ok();
+}
+
+extern "C" const char* tamm_config_name(int32_t precision, int32_t config) {
+  if (precision != TAMM_PREC_F64 || config < 0 || config >= f64_config_count()) return "";
+  return f64_config(config).name;
+}
+
+static bool overlaps(const tamm_tensor* a, const tamm_tensor* b) {
+  if (a->numel == 0 || b->numel == 0) return false;
+  const char* a0 = (const char*)a->dev;
+  const char* b0 = (const char*)b->dev;
+  return a0 < b0 + b->numel * 8 && b0 < a0 + a->numel * 8;
+}
+
+static int check_tensors(const tamm_plan* p) {
+  const tamm_tensor* ts[3] = {p->out, p->lhs, p->rhs};
+  const char* nm[3] = {"out", "lhs", "rhs"};
+  for (int x = 0; x < 3; ++x)
+    if (!ts[x]->bound) return fail(TAMM_ERR_UNBOUND, "%s tensor has no bound storage", nm[x]);
+  if (overlaps(p->out, p->lhs) || overlaps(p->out, p->rhs)) return fail(TAMM_ERR_ARG, "out storage overlaps an operand");
+  return TAMM_OK;
+}
+
+static int check_bound(const tamm_plan* p) {
+  if (!p->ws_bound) return fail(TAMM_ERR_UNBOUND, "plan workspace is not bound (or the configuration changed since binding)");
+  return check_tensors(p);
+}
+
+extern "C" int tamm_plan_screen(tamm_plan* p, void* stream) {
+  if (!p) return fail(TAMM_ERR_ARG, "null plan");
+  int rc = check_bound(p);
+  if (rc != TAMM_OK) return rc;
+  ScreenParams sp{};
+  sp.single = screen_desc(p, p->ws, p->lay);
+  sp.n_items = sp.single.n_blocks;
+  HIP_TRY(launch_screen(sp, (hipStream_t)stream));
+  p->screened = true;
+  return ok();
+}
+
+static int contract_launch(tamm_plan* p, double alpha, double beta, hipStream_t s) {
+  ContractParams cp{};
+  cp.single = problem_desc(p, p->ws, p->lay, p->k_splits > 1 ? (double*)(p->ws + p->off_partial) : nullptr, p->k_splits,
+                           alpha, beta);
+  cp.probs = nullptr;
+  cp.work = (const WorkItem*)(p->ws + p->off_work);
+  cp.next_item = nullptr;
+  cp.n_work = (int32_t)p->work.size();
+  HIP_TRY(launch_contract_f64(p->config, 2 * (p->a_kc ? 1 : 0) + (p->b_kc ? 1 : 0), cp, 0, s));
+  if (p->k_splits > 1) {
+    const F64Config& f = f64_config(p->config);
+    ReduceParams r{};
+    r.single = cp.single;
+    r.probs = nullptr;
+    r.items = (const ReduceItem*)(p->ws + p->off_reduce);
+    r.n_items = (int32_t)p->reduce.size();
+    r.tile_m = f.mt;
+    r.tile_n = f.nt;
+    HIP_TRY(launch_reduce(r, s));
+  }
+  return TAMM_OK;
+}
+
+extern "C" int tamm_plan_contract(tamm_plan* p, double alpha, double beta, void* stream) {
+  if (!p) return fail(TAMM_ERR_ARG, "null plan");
+  int rc = check_bound(p);
+  if (rc != TAMM_OK) return rc;
+  if (!p->screened) return fail(TAMM_ERR_UNBOUND, "the plan has not been screened on its bound workspace");
+  rc = contract_launch(p, alpha, beta, (hipStream_t)stream);
+  if (rc != TAMM_OK) return rc;
+  p->executed = true;
+  return ok();
+}
+
+extern "C" int tamm_plan_execute(tamm_plan* p, double alpha, double beta, void* stream) {
+  int rc = tamm_plan_screen(p, stream);
+  if (rc != TAMM_OK) return rc;
+  return tamm_plan_contract(p, alpha, beta, stream);
+}
+
+extern "C" int tamm_plan_screen_result(tamm_plan* p, void* stream, int32_t* counts, int32_t* k_tiles) {
+  if (!p || !counts) return fail(TAMM_ERR_ARG, "null argument");
+  if (!p->ws_bound || !p->screened) return fail(TAMM_ERR_UNBOUND, "plan has not been screened on a bound workspace");
+  const size_t nob = p->blocks.size();
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  HIP_TRY(hipMemcpy(counts, p->ws + p->lay.counts, nob * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (k_tiles) {
+    std::vector<PairDesc> pairs((size_t)nob * p->n_kt);
+    HIP_TRY(hipMemcpy(pairs.data(), p->ws + p->lay.pairs, pairs.size() * sizeof(PairDesc), hipMemcpyDeviceToHost));
+    const int nk = p->sd.nk;
+    std::vector<int> t(nk);
+    size_t w = 0;
+    for (size_t b = 0; b < nob; ++b)
+      for (int i = 0; i < counts[b]; ++i) {
+        int rem = pairs[b * p->n_kt + i].kt;
+        for (int q = nk - 1; q >= 0; --q) {
+          t[q] = rem % p->sd.k_ntiles[q];
+          rem /= p->sd.k_ntiles[q];
+        }
+        for (int j = 0; j < nk; ++j) k_tiles[w++] = t[p->k_lhs_order[j]];
+      }
+  }
+  return ok();
+}
+
+extern "C" int tamm_plan_destroy(tamm_plan* p) {
+  delete p;
+  return ok();
+}
+
+// ---------------------------------------------------------------------------------------------
+// autotuner (plans)
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+struct CacheEntry {
+  int config, k_splits, grid;
+  double ms;
+};
+
+bool cache_lookup(const char* path, uint64_t sig, const char* kind, CacheEntry& e) {
+  if (!path || !*path) return false;
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    std::string s, k;
+    CacheEntry c{};
+    if (!(is >> s >> k >> c.config >> c.k_splits >> c.grid >> c.ms)) continue;
+    if (k == kind && std::strtoull(s.c_str(), nullptr, 16) == sig) {
+      e = c;
+      found = true;  // the last entry wins
+    }
+  }
+  return found;
+}
+
+void cache_store(const char* path, uint64_t sig, const char* kind, const CacheEntry& e) {
+  if (!path || !*path) return;
+  std::ofstream f(path, std::ios::app);
+  char buf[160];
+  snprintf(buf, sizeof(buf), "%016llx %s %d %d %d %.6f\n", (unsigned long long)sig, kind, e.config, e.k_splits, e.grid, e.ms);
+  f << buf;
+}
+
+}  // namespace
+
+extern "C" int tamm_plan_autotune_workspace_size(const tamm_plan* p, size_t* bytes) {
+  if (!p || !bytes) return fail(TAMM_ERR_ARG, "null argument");
+  tamm_plan tmp = *p;
+  size_t mx = 0;
+  for (int c = 0; c < f64_config_count(); ++c)
+    for (int ks : {1, 2, 4, 8}) {
+      if (configure_work(&tmp, c, ks) != TAMM_OK) continue;
+      mx = std::max(mx, tmp.ws_size);
+    }
+  *bytes = mx;
+  return ok();
+}
+
+extern "C" int tamm_plan_autotune(tamm_plan* p, void* workspace, size_t bytes, void* stream, const char* cache_path,
+                                  int32_t reps) {
+  if (!p) return fail(TAMM_ERR_ARG, "null plan");
+  int rc = check_tensors(p);
+  if (rc != TAMM_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  CacheEntry best{-1, 1, 0, 1e30};
+  if (!cache_lookup(cache_path, p->signature, "plan", best)) {
+    if (reps <= 0) reps = 3;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int64_t ntiles_max = tiles_for(p, 0).first;
+    for (int c = 0; c < f64_config_count(); ++c) {
+      const int64_t nt = tiles_for(p, c).first;
+      for (int ks : {1, 2, 4, 8}) {
+        if (ks > 1 && nt * ks > 4 * std::max<int64_t>(ntiles_max, 2048)) continue;
+        if (configure_work(p, c, ks) != TAMM_OK || p->ws_size > bytes) continue;
+        if ((rc = bind_plan(p, workspace, bytes)) != TAMM_OK) break;
+        // alpha = 0, beta = 1 leaves out unchanged (for finite operands) while doing the full work
+        if ((rc = tamm_plan_execute(p, 0.0, 1.0, stream)) != TAMM_OK) break;
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r)
+          if ((rc = tamm_plan_execute(p, 0.0, 1.0, stream)) != TAMM_OK) break;
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        ms /= reps;
+        if (ms < best.ms) best = CacheEntry{c, ks, 0, ms};
+      }
+      if (rc != TAMM_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != TAMM_OK) return rc;
+    if (best.config < 0) return fail(TAMM_ERR_WORKSPACE, "no configuration fits the %zu-byte workspace", bytes);
+    cache_store(cache_path, p->signature, "plan", best);
+  }
+  rc = configure_work(p, best.config, best.k_splits);
+  if (rc != TAMM_OK) return rc;
+  if (p->ws_size > bytes) return fail(TAMM_ERR_WORKSPACE, "cached configuration needs %zu bytes", p->ws_size);
+  rc = bind_plan(p, workspace, bytes);
+  return rc == TAMM_OK ? ok() : rc;
+}
+
+// ---------------------------------------------------------------------------------------------
+// groups: many independent plans, one screening launch and one persistent contraction launch,
+// optionally captured once into a hipGraph and replayed.
+// ---------------------------------------------------------------------------------------------
+struct tamm_group {
+  std::vector<tamm_plan*> plans;
+  std::vector<Layout> lays;
+  size_t off_sdesc = 0, off_pdesc = 0, off_sitems = 0, off_work = 0, off_counter = 0, ws_size = 0;
+  std::vector<int32_t> sitem_prob, sitem_block;
+  std::vector<WorkItem> work;       // grouped by gather layout class, each class longest first
+  int32_t cls_begin[5] = {0, 0, 0, 0, 0};  // work range of layout class c: [cls_begin[c], cls_begin[c+1])
+  int config = -1;
+  int grid = 0;   // 0: automatic
+  uint64_t signature = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool bound = false;
+  std::vector<ProblemDesc> pdesc;   // host copy (alpha/beta updated per execute)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<double> g_alpha, g_beta;
+};
+
+static void group_drop_graph(tamm_group* g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  g->exec = nullptr;
+  g->graph = nullptr;
+}
+
+static int group_configure(tamm_group* g, int config) {
+  if (config < 0) {
+    // the configuration with the least padding over all members, ties to the larger tile
+    double best = 1e30;
+    for (int c = 0; c < f64_config_count(); ++c) {
+      const F64Config& f = f64_config(c);
+      if (f.kt != 16 || f.wgm * f.wgn != 4 || f.mt > 128 || f.nt > 128) continue;
+      double area = 0, useful = 0;
+      for (auto* p : g->plans)
+        for (const auto& b : p->blocks) {
+          area += (double)((b.mext + f.mt - 1) / f.mt) * f.mt * ((b.next + f.nt - 1) / f.nt) * f.nt;
+          useful += (double)b.mext * b.next;
+        }
+      const double score = (useful > 0 ? area / useful : 1.0) - 1e-6 * f.mt * f.nt;
+      if (score < best) {
+        best = score;
+        config = c;
+      }
+    }
+  }
+  if (config < 0 || config >= f64_config_count()) return fail(TAMM_ERR_ARG, "configuration %d does not exist", config);
+  const F64Config& f = f64_config(config);
+  struct Tile {
+    double cost;
+    WorkItem w;
+  };
+  std::vector<Tile> tiles;
+  for (size_t q = 0; q < g->plans.size(); ++q) {
+    const tamm_plan* p = g->plans[q];
+    int32_t t = 0;
+    for (size_t b = 0; b < p->blocks.size(); ++b) {
+      const auto& d = p->blocks[b];
+      for (int32_t m0 = 0; m0 < d.mext; m0 += f.mt)
+        for (int32_t n0 = 0; n0 < d.next; n0 += f.nt)
+          tiles.push_back(Tile{p->block_cost[b] * std::min(f.mt, d.mext - m0) * std::min(f.nt, d.next - n0),
+                               WorkItem{(int32_t)q, (int32_t)b, m0, n0, 0, t++}});
+    }
+  }
+  std::stable_sort(tiles.begin(), tiles.end(), [](const Tile& x, const Tile& y) { return x.cost > y.cost; });
+  g->work.clear();
+  for (int c = 0; c < 4; ++c) {
+    g->cls_begin[c] = (int32_t)g->work.size();
+    for (auto& t : tiles) {
+      const tamm_plan* p = g->plans[t.w.prob];
+      if (2 * (p->a_kc ? 1 : 0) + (p->b_kc ? 1 : 0) == c) g->work.push_back(t.w);
+    }
+  }
+  g->cls_begin[4] = (int32_t)g->work.size();
+  g->config = config;
+  size_t off = 0;
+  g->lays.clear();
+  for (auto* p : g->plans) {
+    g->lays.push_back(make_layout(p, off));
+    off = g->lays.back().end;
+  }
+  g->off_sdesc = off;
+  off = align256(off + g->plans.size() * sizeof(ScreenDesc));
+  g->off_pdesc = off;
+  off = align256(off + g->plans.size() * sizeof(ProblemDesc));
+  g->off_sitems = off;
+  off = align256(off + g->sitem_prob.size() * 2 * sizeof(int32_t));
+  g->off_work = off;
+  off = align256(off + g->work.size() * sizeof(WorkItem));
+  g->off_counter = off;  // one work counter per layout class
+  off = align256(off + 4 * sizeof(int32_t));
+  g->ws_size = off;
+  g->bound = false;
+  group_drop_graph(g);
+  return TAMM_OK;
+}
+
+extern "C" int tamm_group_create(tamm_plan* const* plans, int32_t n, tamm_group** out) {
+  if (!out) return fail(TAMM_ERR_ARG, "null output pointer");
+  *out = nullptr;
+  if (!plans || n <= 0) return fail(TAMM_ERR_ARG, "a group needs at least one plan");
+  auto g = std::make_unique<tamm_group>();
+  uint64_t h = 0xCBF29CE484222325ULL;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!plans[i]) return fail(TAMM_ERR_ARG, "plan %d is null", i);
+    if (plans[i]->prec != TAMM_PREC_F64) return fail(TAMM_ERR_UNSUPPORTED, "groups run float64 plans only");
+    for (int32_t j = 0; j < i; ++j)
+      if (plans[j]->out == plans[i]->out) return fail(TAMM_ERR_ARG, "plans %d and %d write the same output tensor", j, i);
+    g->plans.push_back(plans[i]);
+    h = fnv(h, &plans[i]->signature, sizeof(uint64_t));
+    for (size_t b = 0; b < plans[i]->blocks.size(); ++b) {
+      g->sitem_prob.push_back(i);
+      g->sitem_block.push_back((int32_t)b);
+    }
+  }
+  g->signature = h;
+  const int rc = group_configure(g.get(), -1);
+  if (rc != TAMM_OK) return rc;
+  *out = g.release();
+  return ok();
+}
+
+extern "C" int tamm_group_workspace_size(const tamm_group* g, size_t* bytes) {
+  if (!g || !bytes) return fail(TAMM_ERR_ARG, "null argument");
+  *bytes = g->ws_size;
+  return ok();
+}
+
+static int group_bind(tamm_group* g, void* dev_ptr, size_t bytes) {
+  if (!dev_ptr || ((uintptr_t)dev_ptr) % 256) return fail(TAMM_ERR_WORKSPACE, "workspace must be non-null and 256-byte aligned");
+  if (bytes < g->ws_size) return fail(TAMM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", bytes, g->ws_size);
+  char* ws = (char*)dev_ptr;
+  std::vector<ScreenDesc> sds;
+  g->pdesc.clear();
+  for (size_t q = 0; q < g->plans.size(); ++q) {
+    int rc = upload_static(g->plans[q], ws, g->lays[q]);
+    if (rc != TAMM_OK) return rc;
+    sds.push_back(screen_desc(g->plans[q], ws, g->lays[q]));
+    g->pdesc.push_back(problem_desc(g->plans[q], ws, g->lays[q], nullptr, 1, 1.0, 0.0));
+  }
+  HIP_TRY(hipMemcpy(ws + g->off_sdesc, sds.data(), sds.size() * sizeof(ScreenDesc), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ws + g->off_pdesc, g->pdesc.data(), g->pdesc.size() * sizeof(ProblemDesc), hipMemcpyHostToDevice));
+  std::vector<int32_t> items(g->sitem_prob);
+  items.insert(items.end(), g->sitem_block.begin(), g->sitem_block.end());
+  if (!items.empty()) HIP_TRY(hipMemcpy(ws + g->off_sitems, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (!g->work.empty()) HIP_TRY(hipMemcpy(ws + g->off_work, g->work.data(), g->work.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+  g->ws = ws;
+  g->ws_bytes = bytes;
+  g->bound = true;
+  group_drop_graph(g);
+  return TAMM_OK;
+}
+
+extern "C" int tamm_group_bind_workspace(tamm_group* g, void* dev_ptr, size_t bytes) {
+  if (!g) return fail(TAMM_ERR_ARG, "null group");
+  const int rc = group_bind(g, dev_ptr, bytes);
+  return rc == TAMM_OK ? ok() : rc;
+}
+
+extern "C" int tamm_group_set_config(tamm_group* g, int32_t config, int32_t grid) {
+  if (!g) return fail(TAMM_ERR_ARG, "null group");
+  if (grid < 0) return fail(TAMM_ERR_ARG, "grid must be >= 0");
+  const int rc = group_configure(g, config);
+  if (rc != TAMM_OK) return rc;
+  g->grid = grid;
+  return ok();
+}
+
+static int group_grid(const tamm_group* g, int n_work) {
+  if (g->grid > 0) return std::max(1, std::min<int>(g->grid, n_work));
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+  }
+  return std::max(1, std::min<int>(2 * cus, n_work));
+}
+
+// Enqueue the group's kernels (counter reset, screening, persistent contraction).
+static int group_enqueue(tamm_group* g, hipStream_t s) {
+  ScreenParams sp{};
+  sp.probs = (const ScreenDesc*)(g->ws + g->off_sdesc);
+  sp.item_prob = (const int32_t*)(g->ws + g->off_sitems);
+  sp.item_block = sp.item_prob + g->sitem_prob.size();
+  sp.n_items = (int32_t)g->sitem_prob.size();
+  HIP_TRY(launch_screen(sp, s));
+  // one persistent launch per operand-layout class present in the group
+  for (int c = 0; c < 4; ++c) {
+    const int n = g->cls_begin[c + 1] - g->cls_begin[c];
+    if (n <= 0) continue;
+    const int grid = group_grid(g, n);
+    int32_t* counter = (int32_t*)(g->ws + g->off_counter) + c;
+    HIP_TRY(launch_set_counter(counter, grid, s));
+    ContractParams cp{};
+    cp.probs = (const ProblemDesc*)(g->ws + g->off_pdesc);
+    cp.work = (const WorkItem*)(g->ws + g->off_work) + g->cls_begin[c];
+    cp.next_item = counter;
+    cp.n_work = n;
+    HIP_TRY(launch_contract_f64(g->config, c, cp, grid, s));
+  }
+  return TAMM_OK;
+}
+
+static int group_check(tamm_group* g) {
+  if (!g->bound) return fail(TAMM_ERR_UNBOUND, "group workspace is not bound (or the configuration changed since binding)");
+  for (auto* p : g->plans) {
+    int rc = check_tensors(p);
+    if (rc != TAMM_OK) return rc;
+  }
+  // members must be independent: no member writes storage that another member reads or writes
+  for (size_t i = 0; i < g->plans.size(); ++i)
+    for (size_t j = 0; j < g->plans.size(); ++j) {
+      if (i == j) continue;
+      const tamm_plan* a = g->plans[i];
+      const tamm_plan* b = g->plans[j];
+      if (overlaps(a->out, b->out) || overlaps(a->out, b->lhs) || overlaps(a->out, b->rhs))
+        return fail(TAMM_ERR_ARG, "group members %zu and %zu are not independent (member %zu writes storage member %zu uses)", i,
+                    j, i, j);
+    }
+  return TAMM_OK;
+}
+
+// Refresh the device problem descriptors when storage bindings or coefficients changed.
+static int group_update_desc(tamm_group* g, const double* alpha, const double* beta, hipStream_t s, bool* changed) {
+  *changed = false;
+  for (size_t q = 0; q < g->plans.size(); ++q) {
+    ProblemDesc d = problem_desc(g->plans[q], g->ws, g->lays[q], nullptr, 1, alpha[q], beta[q]);
+    if (memcmp(&d, &g->pdesc[q], sizeof(d)) != 0) {
+      g->pdesc[q] = d;
+      *changed = true;
+    }
+  }
+  if (*changed) {
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(g->ws + g->off_pdesc, g->pdesc.data(), g->pdesc.size() * sizeof(ProblemDesc), hipMemcpyHostToDevice));
+  }
+  return TAMM_OK;
+}
+
+extern "C" int tamm_group_execute(tamm_group* g, const double* alpha, const double* beta, void* stream) {
+  if (!g || !alpha || !beta) return fail(TAMM_ERR_ARG, "null argument");
+  int rc = group_check(g);
+  if (rc != TAMM_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  bool changed = false;
+  if (g->exec) {
+    const size_t n = g->plans.size();
+    const bool same = std::equal(alpha, alpha + n, g->g_alpha.begin()) && std::equal(beta, beta + n, g->g_beta.begin());
+    if (same) {
+      // the captured graph used the current descriptors; make sure bindings did not move
+      for (size_t q = 0; q < n && !changed; ++q) {
+        ProblemDesc d = problem_desc(g->plans[q], g->ws, g->lays[q], nullptr, 1, alpha[q], beta[q]);
+        changed = memcmp(&d, &g->pdesc[q], sizeof(d)) != 0;
+      }
+      if (!changed) {
+        HIP_TRY(hipGraphLaunch(g->exec, s));
+        return ok();
+      }
+    }
+    group_drop_graph(g);
+  }
+  // eager path: descriptor refresh when something changed (after the stream drained, so that
+  // earlier launches that read the old descriptors are finished), then the three launches
+  rc = group_update_desc(g, alpha, beta, s, &changed);
+  if (rc != TAMM_OK) return rc;
+  rc = group_enqueue(g, s);
+  return rc == TAMM_OK ? ok() : rc;
+}
+
+extern "C" int tamm_group_capture(tamm_group* g, const double* alpha, const double* beta, void* stream) {
+  if (!g || !alpha || !beta) return fail(TAMM_ERR_ARG, "null argument");
+  int rc = group_check(g);
+  if (rc != TAMM_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  bool changed = false;
+  rc = group_update_desc(g, alpha, beta, s, &changed);
+  if (rc != TAMM_OK) return rc;
+  group_drop_graph(g);
+  hipStream_t cs;
+  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return fail(TAMM_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  }
+  rc = group_enqueue(g, cs);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (rc != TAMM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(TAMM_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(TAMM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  g->graph = graph;
+  g->exec = exec;
+  g->g_alpha.assign(alpha, alpha + g->plans.size());
+  g->g_beta.assign(beta, beta + g->plans.size());
+  return ok();
+}
+
+extern "C" int tamm_group_autotune(tamm_group* g, void* stream, const char* cache_path, int32_t reps) {
+  if (!g) return fail(TAMM_ERR_ARG, "null group");
+  int rc = group_check(g);
+  if (rc != TAMM_OK) return rc;
+  void* ws = g->ws;
+  const size_t bytes = g->ws_bytes;
+  hipStream_t s = (hipStream_t)stream;
+  CacheEntry best{-1, 1, 0, 1e30};
+  if (!cache_lookup(cache_path, g->signature, "group", best)) {
+    if (reps <= 0) reps = 3;
+    std::vector<double> a0(g->plans.size(), 0.0), b1(g->plans.size(), 1.0);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    for (int c = 0; c < f64_config_count() && rc == TAMM_OK; ++c) {
+      for (int mult : {1, 2, 4}) {
+        if ((rc = group_configure(g, c)) != TAMM_OK) break;
+        if (g->ws_size > bytes) continue;
+        g->grid = mult * cus;
+        if ((rc = group_bind(g, ws, bytes)) != TAMM_OK) break;
+        // alpha = 0, beta = 1 leaves every output unchanged (finite operands)
+        if ((rc = tamm_group_execute(g, a0.data(), b1.data(), stream)) != TAMM_OK) break;
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < reps && rc == TAMM_OK; ++r) rc = tamm_group_execute(g, a0.data(), b1.data(), stream);
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        ms /= reps;
+        if (ms < best.ms) best = CacheEntry{c, 1, g->grid, ms};
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != TAMM_OK) return rc;
+    if (best.config < 0) return fail(TAMM_ERR_WORKSPACE, "no configuration fits the bound workspace");
+    cache_store(cache_path, g->signature, "group", best);
+  }
+  rc = group_configure(g, best.config);
+  if (rc != TAMM_OK) return rc;
+  g->grid = best.grid;
+  if (g->ws_size > bytes) return fail(TAMM_ERR_WORKSPACE, "cached configuration needs %zu bytes", g->ws_size);
+  rc = group_bind(g, ws, bytes);
+  return rc == TAMM_OK ? ok() : rc;
+}
+
+extern "C" int tamm_group_stats(const tamm_group* g, int32_t* config, int32_t* grid, int64_t* work_items) {
+  if (!g) return fail(TAMM_ERR_ARG, "null group");
+  if (config) *config = g->config;
+  if (grid) *grid = g->grid;
+  if (work_items) *work_items = (int64_t)g->work.size();
+  return ok();
+}
+
+extern "C" int tamm_group_destroy(tamm_group* g) {
+  if (g) group_drop_graph(g);
+  delete g;
+  return ok();
+}

@@ -1,0 +1,141 @@
+"""Grouped persistent launch, hipGraph replay and the autotuner, on a subset of the batched
+workload (independent contractions from random index spaces, mixed term types).
+
+* every member of a group equals the oracle (relative error <= 1e-12 on sampled blocks);
+* the grouped launch equals each member's single launch bitwise when both use the same kernel
+  configuration without K splits (same per-tile summation order);
+* graph replays equal the eager result bitwise, with eager work between the replays;
+* autotuned plans and groups stay within the parity bar.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2201_01257_amd import core as tm
+from paper_2201_01257_amd import synth
+from tests.gpu_util import Problem, max_rel
+
+pytestmark = pytest.mark.gpu
+
+
+def build_member(desc):
+    prob = Problem(desc["n_occ"], desc["n_vir"], desc["tile_occ"], desc["tile_vir"], seed=desc["seed"])
+    (on, op, ol), (ln, lp, ll), (rn, rp, rl), a = synth.TERMS[desc["term"]]
+    L = prob.gpu_tensor(ln, lp)
+    R = prob.gpu_tensor(rn, rp)
+    O = prob.gpu_tensor(on, op)
+    plan = tm.Plan(O, ol, L, ll, R, rl)
+    return dict(prob=prob, L=L, R=R, O=O, plan=plan, alpha=a, labels=(on, op, ol, ln, lp, ll, rn, rp, rl), desc=desc)
+
+
+def subset(max_vir=72, count=20):
+    out = [d for d in synth.batched_problems() if d["n_vir"] <= max_vir]
+    return out[:count]
+
+
+def oracle_blocks(m, tiles):
+    on, op, ol, ln, lp, ll, rn, rp, rl = m["labels"]
+    prob = m["prob"]
+    Oo = prob.oracle_tensor(on, op, lazy=True)
+    Lo = prob.oracle_tensor(ln, lp, lazy=True)
+    Ro = prob.oracle_tensor(rn, rp, lazy=True)
+    return oracle.contract(Oo, ol, Lo, ll, Ro, rl, m["alpha"], 0.0, out_tiles=tiles).blocks
+
+
+def sample_tiles(m, rng, k=2):
+    tiles = [tuple(int(x) for x in t) for t in m["O"].block_tiles]
+    idx = rng.choice(len(tiles), size=min(k, len(tiles)), replace=False)
+    return [tiles[i] for i in idx]
+
+
+def test_group_matches_oracle_and_single_launches_bitwise():
+    members = [build_member(d) for d in subset()]
+    assert len({m["desc"]["term"] for m in members}) >= 4
+    group = tm.Group([m["plan"] for m in members])
+    cfg = group.stats()["config"]
+    alphas = [m["alpha"] for m in members]
+    group.execute(alphas, [0.0] * len(members))
+    torch.cuda.synchronize()
+    grouped = [m["O"].data.clone() for m in members]
+    rng = np.random.default_rng(1)
+    for m, gout in zip(members, grouped):
+        tiles = sample_tiles(m, rng)
+        ref = oracle_blocks(m, tiles)
+        got = m["O"].to_blocks()
+        rel, _ = max_rel(got, ref, keys=tiles)
+        assert rel <= 1e-12, (m["desc"], rel)
+    # single launches with the group's configuration (no K splits) give identical bits
+    for m, gout in zip(members, grouped):
+        m["O"].data.zero_()
+        m["plan"].set_config(cfg, 1)
+        m["plan"].execute(m["alpha"], 0.0)
+    torch.cuda.synchronize()
+    for m, gout in zip(members, grouped):
+        assert torch.equal(m["O"].data, gout), m["desc"]
+
+
+def test_graph_replay_matches_eager_bitwise():
+    members = [build_member(d) for d in subset(count=12)]
+    group = tm.Group([m["plan"] for m in members])
+    alphas = [m["alpha"] for m in members]
+    betas = [0.5] * len(members)
+    init = [torch.randn_like(m["O"].data) for m in members]
+    for m, x in zip(members, init):
+        m["O"].data.copy_(x)
+    group.execute(alphas, betas)
+    torch.cuda.synchronize()
+    eager = [m["O"].data.clone() for m in members]
+    group.capture(alphas, betas)
+    for rep in range(3):
+        for m, x in zip(members, init):
+            m["O"].data.copy_(x)  # eager work between replays
+        scratch = torch.randn(1 << 20, device="cuda") * 2.0
+        scratch.sum().item()
+        group.execute(alphas, betas)  # replays the captured graph
+        torch.cuda.synchronize()
+        for m, e in zip(members, eager):
+            assert torch.equal(m["O"].data, e), (rep, m["desc"])
+
+
+def test_autotune_plan_and_group(tmp_path):
+    cache = str(tmp_path / "tune.txt")
+    members = [build_member(d) for d in subset(count=6)]
+    rng = np.random.default_rng(2)
+    m = members[0]
+    m["plan"].autotune(cache, reps=1)
+    st = m["plan"].stats()
+    m["plan"].execute(m["alpha"], 0.0)
+    torch.cuda.synchronize()
+    tiles = sample_tiles(m, rng)
+    rel, _ = max_rel(m["O"].to_blocks(), oracle_blocks(m, tiles), keys=tiles)
+    assert rel <= 1e-12
+    # a second plan with the same structure reuses the cached choice without measuring
+    again = tm.Plan(m["O"], m["labels"][2], m["L"], m["labels"][5], m["R"], m["labels"][8])
+    again.autotune(cache, reps=1)
+    assert again.stats()["kernel_config"] == st["kernel_config"] and again.stats()["k_splits"] == st["k_splits"]
+    group = tm.Group([x["plan"] for x in members])
+    group.autotune(cache, reps=1)
+    group.execute([x["alpha"] for x in members], [0.0] * len(members))
+    torch.cuda.synchronize()
+    for x in members:
+        tiles = sample_tiles(x, rng, k=1)
+        rel, _ = max_rel(x["O"].to_blocks(), oracle_blocks(x, tiles), keys=tiles)
+        assert rel <= 1e-12
+    lines = open(cache).read().strip().splitlines()
+    assert any(" plan " in ln for ln in lines) and any(" group " in ln for ln in lines)
+
+
+def test_group_rejects_dependent_members():
+    prob = Problem(8, 20, 4, 10)
+    W = prob.gpu_tensor(None, "oooo", fill=False)
+    Voo = prob.gpu_tensor("V_oovv", "oovv")
+    T = prob.gpu_tensor("T2", "vvoo")
+    R = prob.gpu_tensor(None, "vvoo", fill=False)
+    p1 = tm.Plan(W, "mnij", Voo, "mnef", T, "efij")   # writes W
+    p2 = tm.Plan(R, "abij", W, "mnij", T, "abmn")     # reads W
+    grp = tm.Group([p1, p2])
+    with pytest.raises(tm.TammError) as e:
+        grp.execute([1.0, 0.25], [0.0, 1.0])
+    assert e.value.status == "TAMM_ERR_ARG"
