@@ -78,11 +78,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing (parity still checked)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work in the CPU baseline")
     ap.add_argument("--json-out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--precision", default=None, help="mixed workload: one of f64,f32,bf16x3,bf16x4_aligned (default all)")
+    ap.add_argument("--tune-cache", default="", help="autotuner cache file (batched workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1 "
                           "(multi-GPU sharding is described in the design notes, not built)"}))
         sys.exit(2)
+    if args.workload.startswith("mixed"):
+        return run_mixed(args)
+    if args.workload == "batched":
+        return run_batched(args)
+    if args.workload.startswith("adjoint"):
+        return run_adjoint(args)
+    if args.workload == "copycal":
+        return run_copycal(args)
 
     import torch
 
@@ -328,6 +338,256 @@ def _touch(out, ol, lhs, ll, rhs, rl, tile, kts):
         tile_of.update(zip(k_lbl, kt))
         lhs.blocks[tuple(tile_of[c] for c in ll)]
         rhs.blocks[tuple(tile_of[c] for c in rl)]
+
+
+def _emit(args, line):
+    s = json.dumps(line)
+    print(s, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(s + "\n")
+
+
+def _gpu_space(tm, orb, c, tile):
+    na = orb.n_occ_alpha if c == "o" else orb.n_vir_alpha
+    n = orb.n_occ if c == "o" else orb.n_vir
+    return tm.Space.spin(na, n - na, tile)
+
+
+def _oracle_space(oracle, orb, c, tile):
+    na = orb.n_occ_alpha if c == "o" else orb.n_vir_alpha
+    n = orb.n_occ if c == "o" else orb.n_vir
+    return oracle.Space.spin_blocked(na, n - na, tile)
+
+
+def _oracle_tensor(oracle, synth, orb, osp, name, pattern):
+    spaces = [osp[c] for c in pattern]
+    src = synth.input_name(name)
+    x = oracle.BlockTensor(spaces)
+
+    def fill(tile):
+        lo = [spaces[d].offsets[tile[d]] for d in range(len(pattern))]
+        ext = [spaces[d].sizes[tile[d]] for d in range(len(pattern))]
+        return orb.fill(src, pattern, lo, ext)
+
+    x.blocks = oracle.LazyBlocks(fill)
+    return x
+
+
+def _rel(got, ref, keys):
+    num = sum(float(np.sum((got[k] - ref[k]) ** 2)) for k in keys)
+    den = sum(float(np.sum(ref[k] ** 2)) for k in keys)
+    mx = max(float(np.max(np.abs(got[k] - ref[k]))) for k in keys)
+    return (num / den) ** 0.5 if den > 0 else num ** 0.5, mx
+
+
+def _time(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def run_mixed(args):
+    """Ladder + ring at O=64, V=320, tiles of 64, per precision; float64 final accumulation and
+    denominator update; error of each term against the float64 oracle on sampled blocks."""
+    import torch
+
+    import oracle
+    from paper_2201_01257_amd import core as tm
+    from paper_2201_01257_amd import synth
+
+    wl = synth.WORKLOADS[args.workload]
+    orb = synth.Orbitals(wl["n_occ"], wl["n_vir"])
+    g = {c: _gpu_space(tm, orb, c, wl["tile_occ"] if c == "o" else wl["tile_vir"]) for c in "ov"}
+    osp = {c: _oracle_space(oracle, orb, c, wl["tile_occ"] if c == "o" else wl["tile_vir"]) for c in "ov"}
+    T = {}
+    for name, pat in (("V_vvvv", "vvvv"), ("V_ovvo", "ovvo"), ("T2", "vvoo")):
+        t0 = time.time()
+        T[name] = tm.Tensor([g[c] for c in pat])
+        T[name].fill_blocks(lambda lo, ext, out, n=name, p=pat: orb.fill(n, p, lo, ext, out=out))
+        log(f"[bench] generated {name}: {T[name].numel} elements in {time.time() - t0:.1f}s")
+    R = tm.Tensor([g[c] for c in "vvoo"])
+    Tn = tm.Tensor([g[c] for c in "vvoo"])
+    e_o = torch.from_numpy(orb.e_occ).cuda()
+    e_v = torch.from_numpy(orb.e_vir).cuda()
+    denom = tm.Denominator(Tn, R, [e_v, e_v, e_o, e_o], [-1, -1, 1, 1])
+    precisions = [args.precision] if args.precision else ["f64", "f32", "bf16x3", "bf16x4_aligned"]
+    terms = {"ladder": (T["V_vvvv"], "abcd", T["T2"], "cdij", 0.5), "ring": (T["V_ovvo"], "mbej", T["T2"], "aeim", 1.0)}
+    # oracle reference on sampled output blocks of each term (computed once)
+    rng = np.random.default_rng(2201)
+    Ro = oracle.BlockTensor([osp[c] for c in "vvoo"])
+    tiles = Ro.stored_tiles()
+    small = [t for t in tiles if all(osp["v"].sizes[t[d]] < wl["tile_vir"] for d in (0, 1))]
+    pick = [small[i] for i in rng.choice(len(small), size=2, replace=False)]
+    ref = {}
+    t0 = time.perf_counter()
+    for term, (L, ll, Rr, rl, a) in terms.items():
+        lname = "V_vvvv" if term == "ladder" else "V_ovvo"
+        lo = _oracle_tensor(oracle, synth, orb, osp, lname, "vvvv" if term == "ladder" else "ovvo")
+        to = _oracle_tensor(oracle, synth, orb, osp, "T2", "vvoo")
+        ref[term] = oracle.contract(Ro, "abij", lo, ll, to, rl, a, 0.0, out_tiles=pick).blocks
+    log(f"[bench] oracle reference on {len(pick)} blocks per term: {time.perf_counter() - t0:.1f}s")
+    results = {}
+    for prec in precisions:
+        plans = {t: tm.Plan(R, "abij", L, ll, Rr, rl, precision=prec) for t, (L, ll, Rr, rl, a) in terms.items()}
+        errs = {}
+        for t, p in plans.items():
+            p.execute(terms[t][4], 0.0)
+            torch.cuda.synchronize()
+            errs[t] = _rel(R.to_blocks(), ref[t], pick)
+        ms = {}
+        for t, p in plans.items():
+            ms[t] = _time(torch, lambda p=p, a=terms[t][4]: p.execute(a, 0.0), max(2, args.steps // 2), 1)
+
+        def step():
+            plans["ladder"].execute(0.5, 0.0)
+            plans["ring"].execute(1.0, 1.0)
+            denom.execute()
+
+        step_ms = _time(torch, step, max(2, args.steps // 2), 1)
+        fl = {t: p.stats()["useful_flops"] for t, p in plans.items()}
+        results[prec] = {
+            "step_ms": round(step_ms, 3),
+            "step_tflops": round(sum(fl.values()) / step_ms / 1e9, 3),
+            "terms": {t: {"ms": round(ms[t], 3), "tflops": round(fl[t] / ms[t] / 1e9, 3), "rel_err": float(f"{errs[t][0]:.3e}"),
+                          "max_abs_err": float(f"{errs[t][1]:.3e}"), "config": p.config_name()} for t, p in plans.items()},
+        }
+        log(f"[bench] {prec}: {results[prec]}")
+        del plans
+        torch.cuda.empty_cache()
+    _emit(args, {"metric": METRIC, "workload": args.workload, "unit": "TFLOP/s", "data": "synthetic",
+                 "sampled_blocks": [list(map(int, t)) for t in pick], "results": results,
+                 "peaks_tflops": {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}})
+
+
+def run_batched(args):
+    """256 independent contractions (random index spaces, mixed terms) as one group: screening +
+    persistent contraction, autotuned, captured once into a hipGraph and replayed."""
+    import torch
+
+    import oracle
+    from paper_2201_01257_amd import core as tm
+    from paper_2201_01257_amd import synth
+
+    probs = synth.batched_problems()
+    members = []
+    t0 = time.time()
+    for d in probs:
+        orb = synth.Orbitals(d["n_occ"], d["n_vir"], seed=d["seed"])
+        g = {c: _gpu_space(tm, orb, c, d["tile_occ"] if c == "o" else d["tile_vir"]) for c in "ov"}
+        (on, op, ol), (ln, lp, ll), (rn, rp, rl), a = synth.TERMS[d["term"]]
+        ts = {}
+        for name, pat in ((ln, lp), (rn, rp)):
+            t = tm.Tensor([g[c] for c in pat])
+            src = synth.input_name(name)
+            t.fill_blocks(lambda lo, ext, out, s_=src, p_=pat: orb.fill(s_, p_, lo, ext, out=out))
+            ts[name] = t
+        O = tm.Tensor([g[c] for c in op])
+        plan = tm.Plan(O, ol, ts[ln], ll, ts[rn], rl, bind=False)
+        members.append(dict(desc=d, orb=orb, O=O, L=ts[ln], R=ts[rn], plan=plan, alpha=a))
+    log(f"[bench] built {len(members)} problems in {time.time() - t0:.1f}s")
+    group = tm.Group([m["plan"] for m in members])
+    alphas = [m["alpha"] for m in members]
+    betas = [0.0] * len(members)
+    t0 = time.time()
+    group.autotune(args.tune_cache, reps=2)
+    log(f"[bench] autotuned group in {time.time() - t0:.1f}s: {group.stats()}")
+    eager_ms = _time(torch, lambda: group.execute(alphas, betas), args.steps, args.warmup)
+    group.capture(alphas, betas)
+    graph_ms = _time(torch, lambda: group.execute(alphas, betas), args.steps, args.warmup)
+    flops = sum(m["plan"].stats()["useful_flops"] for m in members)
+    # parity on sampled problems (one block each)
+    rng = np.random.default_rng(7)
+    worst = 0.0
+    for i in rng.choice(len(members), size=16, replace=False):
+        m = members[int(i)]
+        d = m["desc"]
+        (on, op, ol), (ln, lp, ll), (rn, rp, rl), a = synth.TERMS[d["term"]]
+        osp = {c: _oracle_space(oracle, m["orb"], c, d["tile_occ"] if c == "o" else d["tile_vir"]) for c in "ov"}
+        tiles = [tuple(int(x) for x in t) for t in m["O"].block_tiles]
+        pick = [tiles[int(rng.integers(0, len(tiles)))]]
+        ref = oracle.contract(_oracle_tensor(oracle, synth, m["orb"], osp, on, op), ol,
+                              _oracle_tensor(oracle, synth, m["orb"], osp, ln, lp), ll,
+                              _oracle_tensor(oracle, synth, m["orb"], osp, rn, rp), rl, a, 0.0, out_tiles=pick).blocks
+        worst = max(worst, _rel(m["O"].to_blocks(), ref, pick)[0])
+    if worst > 1e-12:
+        raise SystemExit(f"batched parity failure: {worst}")
+    st = group.stats()
+    _emit(args, {"metric": METRIC, "workload": "batched", "value": round(flops / graph_ms / 1e9, 4), "unit": "TFLOP/s",
+                 "dtype": "f64", "data": "synthetic", "problems": len(members), "useful_gflop": round(flops / 1e9, 2),
+                 "graph_ms": round(graph_ms, 3), "eager_ms": round(eager_ms, 3),
+                 "eager_tflops": round(flops / eager_ms / 1e9, 3), "config": st, "rel_err_max_sampled": float(f"{worst:.3e}"),
+                 "roofline": {"bound": "mfma", "achieved": round(flops / graph_ms / 1e9, 3), "peak": PEAK_F64_MFMA_TFLOPS,
+                              "unit": "TFLOP/s", "frac": round(flops / graph_ms / 1e9 / PEAK_F64_MFMA_TFLOPS, 4)}})
+
+
+def run_adjoint(args):
+    """Forward ladder + ring and the hand-written backward (dT, dV) at O=32, V=160, tiles 32."""
+    import torch
+
+    import oracle
+    from paper_2201_01257_amd import core as tm
+    from paper_2201_01257_amd import synth
+    from paper_2201_01257_amd.autograd import Contraction
+
+    wl = synth.WORKLOADS[args.workload]
+    orb = synth.Orbitals(wl["n_occ"], wl["n_vir"])
+    g = {c: _gpu_space(tm, orb, c, wl["tile_occ"] if c == "o" else wl["tile_vir"]) for c in "ov"}
+    T = {}
+    for name, pat in (("V_vvvv", "vvvv"), ("V_ovvo", "ovvo"), ("T2", "vvoo")):
+        T[name] = tm.Tensor([g[c] for c in pat])
+        T[name].fill_blocks(lambda lo, ext, out, n=name, p=pat: orb.fill(n, p, lo, ext, out=out))
+    R = tm.Tensor([g[c] for c in "vvoo"], device=None)
+    lad = Contraction(R, "abij", T["V_vvvv"], "abcd", T["T2"], "cdij", 0.5, 0.0)
+    ring = Contraction(R, "abij", T["V_ovvo"], "mbej", T["T2"], "aeim", 1.0, 1.0)
+    v = T["V_vvvv"].data[:T["V_vvvv"].numel].clone().requires_grad_(True)
+    vr = T["V_ovvo"].data[:T["V_ovvo"].numel].clone().requires_grad_(True)
+    t = T["T2"].data[:T["T2"].numel].clone().requires_grad_(True)
+
+    def fwd():
+        r = ring(vr, t, lad(v, t))
+        return r, 0.5 * (r * r).sum()
+
+    def fwd_only():
+        with torch.no_grad():
+            fwd()
+
+    def fwd_bwd():
+        v.grad = vr.grad = t.grad = None
+        _, L = fwd()
+        L.backward()
+
+    f_ms = _time(torch, fwd_only, args.steps, args.warmup)
+    fb_ms = _time(torch, fwd_bwd, args.steps, args.warmup)
+    fl_f = sum(p.stats()["useful_flops"] for c in (lad, ring) for k, p in c._plans.items() if k == "fwd")
+    fl_b = sum(p.stats()["useful_flops"] for c in (lad, ring) for k, p in c._plans.items() if k != "fwd")
+    _emit(args, {"metric": METRIC, "workload": args.workload, "unit": "TFLOP/s", "dtype": "f64", "data": "synthetic",
+                 "forward_ms": round(f_ms, 3), "forward_tflops": round(fl_f / f_ms / 1e9, 3),
+                 "forward_backward_ms": round(fb_ms, 3),
+                 "backward_tflops": round(fl_b / max(fb_ms - f_ms, 1e-9) / 1e9, 3),
+                 "useful_gflop": {"forward": round(fl_f / 1e9, 2), "backward": round(fl_b / 1e9, 2)},
+                 "note": "forward_backward includes the elementwise loss; parity of these gradients is tested in tests"})
+
+
+def run_copycal(args):
+    """A plain device copy of known size (torch's copy kernel): the calibration run for the HBM
+    traffic counters (FETCH_SIZE / WRITE_SIZE per dispatch against known bytes)."""
+    import torch
+
+    n = 1 << 28  # 2 GiB of float64 read, 2 GiB written per dispatch
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    ms = _time(torch, lambda: dst.copy_(src), max(1, args.steps), 1)
+    _emit(args, {"workload": "copycal", "bytes_read_per_dispatch": n * 8, "bytes_written_per_dispatch": n * 8,
+                 "ms": round(ms, 4), "GB_per_s": round(2 * n * 8 / ms / 1e6, 1)})
 
 
 if __name__ == "__main__":

@@ -50,21 +50,24 @@ typedef enum {
   TAMM_ERR_HIP = -8          /* a HIP runtime call failed                                     */
 } tamm_status;
 
-/* Compute precision of a contraction.  Storage is always IEEE float64.
- *   F64     : float64 products and float64 accumulation (v_mfma_f64_16x16x4_f64).
- *   F32     : operands rounded to float32 (round to nearest even), float32 matrix-core
- *             products and float32 accumulation inside a K chunk, chunk sums added in float64,
- *             float64 epilogue.
- *   BF16X3  : each operand split into three bfloat16 terms x = b0 + b1 + b2 (b0 = bf16(x),
- *             b1 = bf16(x - b0), b2 = bf16(x - b0 - b1)); the six products b_i*b_j with
- *             i + j <= 2 on bfloat16 matrix cores with float32 accumulation inside a K chunk,
- *             chunk sums added in float64, float64 epilogue.
- *   BF16X3_EXACT : as BF16X3, except that the leading term of every row of A and every column
- *             of B is a fixed-point slice aligned to the row/column maximum exponent, so that
- *             the dominant product is accumulated exactly inside a K chunk (see the design notes
- *             for its error model).
- */
-typedef enum { TAMM_PREC_F64 = 0, TAMM_PREC_F32 = 1, TAMM_PREC_BF16X3 = 2, TAMM_PREC_BF16X3_EXACT = 3 } tamm_precision;
+/* Compute precision of a contraction.  Storage, the final accumulation and the epilogue are
+ * always IEEE float64; float32 partial sums are promoted to float64 after every K window of 256
+ * flattened summed indices (windows start at each tile pair's first index).
+ *   F64    : float64 products and accumulation (v_mfma_f64_16x16x4_f64).
+ *   F32    : operands rounded to float32 (round to nearest even) as they are gathered;
+ *            float32 matrix-core products (v_mfma_f32_16x16x4_f32) summed in float32 per window.
+ *   BF16X3 : each operand split into three bfloat16 terms, x ~ b0 + b1 + b2 with
+ *            b_i = bf16(x - b_0 - ... - b_{i-1}) (round to nearest even); the six products
+ *            b_i*b_j with i + j <= 2 on bfloat16 matrix cores (v_mfma_f32_16x16x32_bf16),
+ *            summed in float32 per window.
+ *   BF16X4_ALIGNED : the leading term of every element is x rounded to the fixed-point grid 8
+ *            bits below the maximum exponent of its (row, window) -- exact in bfloat16 -- and the
+ *            residual is split into three bfloat16 terms; the ten products of term order
+ *            i + j <= 3.  Lead*lead products of one window sum exactly in float32 (kept in their
+ *            own accumulator); only the residual products see float32 rounding.
+ * The split precisions first write the split operands into the plan workspace (one packed
+ * 64-bit word per element); their workspace is correspondingly larger. */
+typedef enum { TAMM_PREC_F64 = 0, TAMM_PREC_F32 = 1, TAMM_PREC_BF16X3 = 2, TAMM_PREC_BF16X4_ALIGNED = 3 } tamm_precision;
 
 /* User non-zero check (Sec. III-A: a user-defined non-zero check used both for allocation and
  * for operation execution).  Called once per tile tuple when a tensor is created, with the

@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import NONZERO_FN, PlanStats, TammError, check, load
 
-PRECISIONS = {"f64": 0, "f32": 1, "bf16x3": 2, "bf16x3_exact": 3}
+PRECISIONS = {"f64": 0, "f32": 1, "bf16x3": 2, "bf16x4_aligned": 3}
 
 
 def _torch():

@@ -240,8 +240,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f64(ContractParams 
           }
           if (has2) load_kofs(d1, k1);
         }
-        const int ksteps = (kc_now + 3) >> 2;
-        for (int s = 0; s < ksteps; ++s) {
+        // All KT/4 k-steps run, fully unrolled so that the LDS reads of step s+1 overlap the
+        // MFMAs of step s; a ragged last chunk of a pair holds zeros beyond its K extent.
+        (void)kc_now;
+#pragma unroll
+        for (int s = 0; s < KT / 4; ++s) {
           const int k = 4 * s + lq;
           double af[FM], bf[FN];
 #pragma unroll

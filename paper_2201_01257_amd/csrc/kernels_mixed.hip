@@ -1,3 +1,588 @@
-// Mixed-precision contraction kernels (float32 and split-bfloat16 products with float64
-// promotion).
+// Mixed-precision contraction kernels for gfx950: the bulk products run on float32 or bfloat16
+// matrix cores with float32 accumulation inside K windows of 256, and every window's partial
+// sums are promoted into float64 accumulators; the epilogue (beta*C + alpha*acc) is float64.
+//
+//   float32 (v_mfma_f32_16x16x4_f32): operands rounded to float32 (round to nearest even) while
+//       they are gathered into LDS.
+//   split bfloat16 (v_mfma_f32_16x16x32_bf16): each operand is first split by k_prep_split into
+//       bfloat16 slices stored as one packed 64-bit word per element (slice s in bits 16s..16s+15),
+//       at the same element offsets as the float64 operand; the contraction then multiplies
+//       selected slice pairs.
+//         - three plain slices (x ~ b0 + b1 + b2, b_i = bf16(x - b_0 - ... - b_{i-1})), the six
+//           products b_i*b_j with i + j <= 2, one float32 accumulator per window;
+//         - aligned lead: slice 0 is x rounded to a fixed-point grid of 8 bits below the maximum
+//           exponent of its (row, window) -- an integer of magnitude <= 256 times a power of two,
+//           exact in bfloat16 -- and slices 1..3 are bfloat16 slices of the residual; the ten
+//           products of slice order i + j <= 3.  Within one 256-long window every lead*lead
+//           product is an integer of at most 16 bits times the same power of two for a given
+//           (m, n), so their sum (at most 2^24 in magnitude) is exact in float32; it is kept in
+//           its own accumulator, and only the small residual products see float32 rounding.
 #include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "mixed.h"
+
+namespace tamm {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------------------------
+// operand split
+// ---------------------------------------------------------------------------------------------
+// Round to nearest even at 8 significant bits (the bfloat16 precision), in float64 arithmetic.
+// Magnitudes below 2^-100 are flushed to zero (far below anything the slices can carry).
+__device__ __forceinline__ double round_bf16(double x) {
+  const double ax = fabs(x);
+  if (!(ax >= 0x1p-100)) return 0.0;
+  const int e = ilogb(x);
+  const double q = ldexp(1.0, e - 7);
+  return rint(x / q) * q;
+}
+
+// Bits of a value that is exactly representable in bfloat16.
+__device__ __forceinline__ uint64_t bf16_bits(double y) {
+  const float f = (float)y;  // exact: y has at most 8 significant bits and a float exponent
+  return (uint64_t)(__float_as_uint(f) >> 16);
+}
+
+__device__ __forceinline__ uint64_t split_plain(double x) {
+  const double b0 = round_bf16(x);
+  const double r1 = x - b0;
+  const double b1 = round_bf16(r1);
+  const double b2 = round_bf16(r1 - b1);
+  return bf16_bits(b0) | (bf16_bits(b1) << 16) | (bf16_bits(b2) << 32);
+}
+
+// scale = 2^(e-8) where 2^e > max |x| of the (row, window)
+__device__ __forceinline__ uint64_t split_aligned(double x, double scale) {
+  const double lead = rint(x / scale) * scale;  // |lead / scale| <= 256
+  const double r = x - lead;                    // exact
+  const double s1 = round_bf16(r);
+  const double r2 = r - s1;
+  const double s2 = round_bf16(r2);
+  const double s3 = round_bf16(r2 - s2);
+  return bf16_bits(lead) | (bf16_bits(s1) << 16) | (bf16_bits(s2) << 32) | (bf16_bits(s3) << 48);
+}
+
+__device__ __forceinline__ double window_scale(double mx) {
+  if (!(mx > 0.0)) return 1.0;
+  int e;
+  frexp(mx, &e);  // mx = f * 2^e, f in [0.5, 1): 2^e > mx
+  return ldexp(1.0, e - 8);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ int find_block(const PrepBlock* blocks, int n, int64_t item) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (blocks[mid].item0 <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One wave per item.  ROWS_ALONG_LANES = false: the operand's stride-1 label is summed, so an item
+// is one (block, row, window) and the lanes run along k (coalesced); the window maximum is a wave
+// reduction.  ROWS_ALONG_LANES = true: an item is (block, 64 rows, window), each lane owns a row
+// and walks the window (lanes coalesce along the row label).
+template <bool ROWS_ALONG_LANES>
+__global__ __launch_bounds__(256) void k_prep_split(PrepParams P) {
+  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= P.n_items) return;
+  const int lane = threadIdx.x & 63;
+  const int b = find_block(P.blocks, P.n_blocks, item);
+  const PrepBlock pb = P.blocks[b];
+  const int64_t local = item - pb.item0;
+  const int win = (int)(local % pb.nwin);
+  const int rg = (int)(local / pb.nwin);
+  const int k0 = win * kSplitWindow;
+  const int k1 = min(pb.kext, k0 + kSplitWindow);
+  const int32_t* __restrict__ pool = P.pool;
+  if (!ROWS_ALONG_LANES) {
+    const int row = rg;
+    const int64_t rowoff = pb.off + pool[pb.tab_row + row];
+    double x[kSplitWindow / 64];
+    double mx = 0.0;
+#pragma unroll
+    for (int j = 0; j < kSplitWindow / 64; ++j) {
+      const int k = k0 + lane + 64 * j;
+      x[j] = (k < k1) ? P.x[rowoff + pool[pb.tab_k + k]] : 0.0;
+      mx = fmax(mx, fabs(x[j]));
+    }
+    const double scale = window_scale(wave_max(mx));
+#pragma unroll
+    for (int j = 0; j < kSplitWindow / 64; ++j) {
+      const int k = k0 + lane + 64 * j;
+      if (k < k1) P.out[rowoff + pool[pb.tab_k + k]] = P.aligned ? split_aligned(x[j], scale) : split_plain(x[j]);
+    }
+  } else {
+    const int row = rg * 64 + lane;
+    if (row >= pb.rows) return;
+    const int64_t rowoff = pb.off + pool[pb.tab_row + row];
+    double mx = 0.0;
+    if (P.aligned)
+      for (int k = k0; k < k1; ++k) mx = fmax(mx, fabs(P.x[rowoff + pool[pb.tab_k + k]]));
+    const double scale = window_scale(mx);
+    for (int k = k0; k < k1; ++k) {
+      const int64_t a = rowoff + pool[pb.tab_k + k];
+      const double v = P.x[a];
+      P.out[a] = P.aligned ? split_aligned(v, scale) : split_plain(v);
+    }
+  }
+}
+
+hipError_t launch_prep_split(const PrepParams& p, bool rows_along_lanes, hipStream_t s) {
+  if (p.n_items <= 0) return hipSuccess;
+  const dim3 g((unsigned)((p.n_items + 3) / 4)), b(256);
+  if (rows_along_lanes) hipLaunchKernelGGL(k_prep_split<true>, g, b, 0, s, p);
+  else hipLaunchKernelGGL(k_prep_split<false>, g, b, 0, s, p);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Shared gather pipeline of the mixed kernels (same structure as the float64 kernel: offset-table
+// entries one chunk ahead, data one chunk ahead, MFMAs on the chunk in LDS).
+// ---------------------------------------------------------------------------------------------
+template <int MT, int NT, int KT, int NTHR, bool A_KC, bool B_KC, typename T>
+struct Gather {
+  static constexpr int AE = MT * KT / NTHR;
+  static constexpr int BE = NT * KT / NTHR;
+  static constexpr int A_NR = A_KC ? AE : 1, A_NK = A_KC ? 1 : AE;
+  static constexpr int B_NR = B_KC ? BE : 1, B_NK = B_KC ? 1 : BE;
+  static constexpr int A_DR = A_KC ? NTHR / KT : 0, A_DK = A_KC ? 0 : NTHR / MT;
+  static constexpr int B_DR = B_KC ? NTHR / KT : 0, B_DK = B_KC ? 0 : NTHR / NT;
+  static_assert(!A_KC || (NTHR % KT == 0 && MT % (NTHR / KT) == 0), "k-contiguous A gather mapping");
+  static_assert(!B_KC || (NTHR % KT == 0 && NT % (NTHR / KT) == 0), "k-contiguous B gather mapping");
+  static_assert(A_KC || (NTHR % MT == 0 && KT % (NTHR / MT) == 0), "m-contiguous A gather mapping");
+  static_assert(B_KC || (NTHR % NT == 0 && KT % (NTHR / NT) == 0), "n-contiguous B gather mapping");
+  int a_k0, a_r0, b_k0, b_r0;
+  int64_t a_row[A_NR], b_row[B_NR];
+  int a_kof[A_NK], b_kof[B_NK];
+  T ra[AE], rb[BE];
+  __device__ void init(int tid) {
+    a_k0 = A_KC ? tid % KT : tid / MT;
+    a_r0 = A_KC ? tid / KT : tid % MT;
+    b_k0 = B_KC ? tid % KT : tid / NT;
+    b_r0 = B_KC ? tid / KT : tid % NT;
+  }
+  __device__ void setup_pair(const PairDesc& d, const int32_t* pool, int m0, int n0, int mext, int next) {
+#pragma unroll
+    for (int e = 0; e < A_NR; ++e) {
+      const int m = m0 + a_r0 + e * A_DR;
+      a_row[e] = (m < mext) ? d.a_off + pool[d.a_tabM + m] : -1;
+    }
+#pragma unroll
+    for (int e = 0; e < B_NR; ++e) {
+      const int n = n0 + b_r0 + e * B_DR;
+      b_row[e] = (n < next) ? d.b_off + pool[d.b_tabN + n] : -1;
+    }
+  }
+  __device__ void load_kofs(const PairDesc& d, const int32_t* pool, int kbase) {
+#pragma unroll
+    for (int e = 0; e < A_NK; ++e) {
+      const int k = kbase + a_k0 + e * A_DK;
+      a_kof[e] = (k < d.kext) ? pool[d.a_tabK + k] : -1;
+    }
+#pragma unroll
+    for (int e = 0; e < B_NK; ++e) {
+      const int k = kbase + b_k0 + e * B_DK;
+      b_kof[e] = (k < d.kext) ? pool[d.b_tabK + k] : -1;
+    }
+  }
+  __device__ void load_data(const T* Ag, const T* Bg) {
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
+      const int64_t r = a_row[A_KC ? e : 0];
+      const int k = a_kof[A_KC ? 0 : e];
+      ra[e] = (r >= 0 && k >= 0) ? Ag[r + k] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < BE; ++e) {
+      const int64_t r = b_row[B_KC ? e : 0];
+      const int k = b_kof[B_KC ? 0 : e];
+      rb[e] = (r >= 0 && k >= 0) ? Bg[r + k] : T(0);
+    }
+  }
+  __device__ int a_lds_row(int e) const { return a_r0 + e * A_DR; }
+  __device__ int a_lds_k(int e) const { return a_k0 + e * A_DK; }
+  __device__ int b_lds_row(int e) const { return b_r0 + e * B_DR; }
+  __device__ int b_lds_k(int e) const { return b_k0 + e * B_DK; }
+};
+
+// Epilogue shared by the mixed kernels: float64 accumulators in the float32 MFMA layout (D[m][n]
+// in lane n + 16*(m/4), register m%4).
+template <int MT, int NT, int WM, int WN, int FM, int FN>
+__device__ __forceinline__ void epilogue_f32layout(const ProblemDesc& pr, const WorkItem& w, const OutBlockDesc& blk,
+                                                   d4_t (&acc)[FM][FN], int wm, int wn, int lr, int lq) {
+  if (pr.k_splits > 1) {
+    double* part = pr.partial + ((int64_t)w.tile * pr.k_splits + w.split) * (MT * NT);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[(wm * WM + i * 16 + 4 * lq + r) * NT + wn * WN + j * 16 + lr] = acc[i][j][r];
+    return;
+  }
+  const double alpha = pr.alpha, beta = pr.beta;
+  const int32_t* pool = pr.pool;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = w.m0 + wm * WM + i * 16 + 4 * lq + r;
+      if (m >= blk.mext) continue;
+      const int64_t rowoff = blk.c_off + pool[blk.c_tabM + m];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int n = w.n0 + wn * WN + j * 16 + lr;
+        if (n >= blk.next) continue;
+        const int64_t idx = rowoff + pool[blk.c_tabN + n];
+        const double v = alpha * acc[i][j][r];
+        pr.C[idx] = (beta == 0.0) ? v : beta * pr.C[idx] + v;
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// float32 products (v_mfma_f32_16x16x4_f32), float32 window sums promoted to float64.
+// ---------------------------------------------------------------------------------------------
+template <int MT, int NT, int KT, int WGM, int WGN, bool A_KC, bool B_KC>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams P) {
+  constexpr int NTHR = 64 * WGM * WGN;
+  constexpr int WM = MT / WGM, WN = NT / WGN, FM = WM / 16, FN = WN / 16;
+  constexpr int LD = KT + 4;  // floats; rows 16 apart land on distinct banks for the 4 k lanes
+  static_assert(kSplitWindow % KT == 0, "chunks tile the promotion window");
+  using G = Gather<MT, NT, KT, NTHR, A_KC, B_KC, double>;
+  __shared__ float As[MT * LD];
+  __shared__ float Bs[NT * LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM, lr = lane & 15, lq = lane >> 4;
+  const int item = blockIdx.x;
+  if (item >= P.n_work) return;
+  const WorkItem w = P.work[item];
+  const ProblemDesc& pr = P.probs ? P.probs[w.prob] : P.single;
+  const OutBlockDesc blk = pr.blocks[w.ob];
+  const int32_t* __restrict__ pool = pr.pool;
+  const PairDesc* __restrict__ pairs = pr.pairs + blk.pair_base;
+  const int cnt = pr.counts[w.ob];
+  int pb = 0, pe = cnt;
+  if (pr.k_splits > 1) {
+    pb = (int)(((int64_t)cnt * w.split) / pr.k_splits);
+    pe = (int)(((int64_t)cnt * (w.split + 1)) / pr.k_splits);
+  }
+  G g;
+  g.init(tid);
+  d4_t acc[FM][FN];
+  f4_t part[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      acc[i][j] = (d4_t){0.0, 0.0, 0.0, 0.0};
+      part[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
+    }
+  if (pb < pe) {
+    PairDesc d1 = pairs[pb];
+    int p1 = pb, k1 = 0;
+    g.setup_pair(d1, pool, w.m0, w.n0, blk.mext, blk.next);
+    g.load_kofs(d1, pool, 0);
+    g.load_data(pr.A, pr.B);
+    int kc_c = min(KT, d1.kext), kpos_c = 0, kext_c = d1.kext;
+    auto advance = [&]() {
+      k1 += KT;
+      bool ok = true;
+      if (k1 >= d1.kext) {
+        ++p1;
+        k1 = 0;
+        if (p1 < pe) {
+          d1 = pairs[p1];
+          g.setup_pair(d1, pool, w.m0, w.n0, blk.mext, blk.next);
+        } else {
+          ok = false;
+        }
+      }
+      if (ok) g.load_kofs(d1, pool, k1);
+      return ok;
+    };
+    bool has1 = advance();
+    while (true) {
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < G::AE; ++e) As[g.a_lds_row(e) * LD + g.a_lds_k(e)] = (float)g.ra[e];
+#pragma unroll
+      for (int e = 0; e < G::BE; ++e) Bs[g.b_lds_row(e) * LD + g.b_lds_k(e)] = (float)g.rb[e];
+      __syncthreads();
+      const int kc_now = kc_c, kpos_now = kpos_c, kext_now = kext_c;
+      bool has2 = false;
+      if (has1) {
+        g.load_data(pr.A, pr.B);
+        kc_c = min(KT, d1.kext - k1);
+        kpos_c = k1;
+        kext_c = d1.kext;
+        has2 = advance();
+      }
+#pragma unroll
+      for (int s = 0; s < KT / 4; ++s) {  // zeros beyond a ragged chunk's K extent
+        float af[FM], bf[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) af[i] = As[(wm * WM + i * 16 + lr) * LD + 4 * s + lq];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) bf[j] = Bs[(wn * WN + j * 16 + lr) * LD + 4 * s + lq];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], part[i][j], 0, 0, 0);
+      }
+      const int kend = kpos_now + kc_now;
+      if (kend % kSplitWindow == 0 || kend >= kext_now) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              acc[i][j][r] += (double)part[i][j][r];
+              part[i][j][r] = 0.f;
+            }
+      }
+      if (!has1) break;
+      has1 = has2;
+    }
+  }
+  epilogue_f32layout<MT, NT, WM, WN, FM, FN>(pr, w, blk, acc, wm, wn, lr, lq);
+}
+
+// ---------------------------------------------------------------------------------------------
+// split bfloat16 products (v_mfma_f32_16x16x32_bf16).  LDS holds NS slice planes per operand as
+// [row][k] bfloat16 with a row stride of KT+8 elements (an odd number of 16-byte units, so the
+// 16-byte fragment reads of 16 consecutive rows hit distinct banks).
+// ---------------------------------------------------------------------------------------------
+template <int MT, int NT, int KT, int WGM, int WGN, bool ALIGNED, bool A_KC, bool B_KC>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParams P) {
+  constexpr int NTHR = 64 * WGM * WGN;
+  constexpr int WM = MT / WGM, WN = NT / WGN, FM = WM / 16, FN = WN / 16;
+  constexpr int NS = ALIGNED ? 4 : 3;
+  constexpr int LD = KT + 8;
+  static_assert(KT % 32 == 0 && kSplitWindow % KT == 0, "chunks of whole MFMA k-steps tile the window");
+  static_assert(((LD * 2) / 16) % 2 == 1, "row stride must be an odd number of 16-byte units");
+  using G = Gather<MT, NT, KT, NTHR, A_KC, B_KC, uint64_t>;
+  __shared__ __attribute__((aligned(16))) __bf16 As[NS * MT * LD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[NS * NT * LD];
+  unsigned short* As16 = reinterpret_cast<unsigned short*>(As);
+  unsigned short* Bs16 = reinterpret_cast<unsigned short*>(Bs);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WGM, wn = wave / WGM, lr = lane & 15, lq = lane >> 4;
+  const int item = blockIdx.x;
+  if (item >= P.n_work) return;
+  const WorkItem w = P.work[item];
+  const ProblemDesc& pr = P.probs ? P.probs[w.prob] : P.single;
+  const OutBlockDesc blk = pr.blocks[w.ob];
+  const int32_t* __restrict__ pool = pr.pool;
+  const PairDesc* __restrict__ pairs = pr.pairs + blk.pair_base;
+  const uint64_t* Ap = reinterpret_cast<const uint64_t*>(pr.A);
+  const uint64_t* Bp = reinterpret_cast<const uint64_t*>(pr.B);
+  const int cnt = pr.counts[w.ob];
+  int pb = 0, pe = cnt;
+  if (pr.k_splits > 1) {
+    pb = (int)(((int64_t)cnt * w.split) / pr.k_splits);
+    pe = (int)(((int64_t)cnt * (w.split + 1)) / pr.k_splits);
+  }
+  G g;
+  g.init(tid);
+  d4_t acc[FM][FN];
+  f4_t lead[FM][FN], rest[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      acc[i][j] = (d4_t){0.0, 0.0, 0.0, 0.0};
+      lead[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
+      rest[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
+    }
+  if (pb < pe) {
+    PairDesc d1 = pairs[pb];
+    int p1 = pb, k1 = 0;
+    g.setup_pair(d1, pool, w.m0, w.n0, blk.mext, blk.next);
+    g.load_kofs(d1, pool, 0);
+    g.load_data(Ap, Bp);
+    int kc_c = min(KT, d1.kext), kpos_c = 0, kext_c = d1.kext;
+    auto advance = [&]() {
+      k1 += KT;
+      bool ok = true;
+      if (k1 >= d1.kext) {
+        ++p1;
+        k1 = 0;
+        if (p1 < pe) {
+          d1 = pairs[p1];
+          g.setup_pair(d1, pool, w.m0, w.n0, blk.mext, blk.next);
+        } else {
+          ok = false;
+        }
+      }
+      if (ok) g.load_kofs(d1, pool, k1);
+      return ok;
+    };
+    bool has1 = advance();
+    while (true) {
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < G::AE; ++e) {
+        const int o = g.a_lds_row(e) * LD + g.a_lds_k(e);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) As16[s * MT * LD + o] = (unsigned short)(g.ra[e] >> (16 * s));
+      }
+#pragma unroll
+      for (int e = 0; e < G::BE; ++e) {
+        const int o = g.b_lds_row(e) * LD + g.b_lds_k(e);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) Bs16[s * NT * LD + o] = (unsigned short)(g.rb[e] >> (16 * s));
+      }
+      __syncthreads();
+      const int kc_now = kc_c, kpos_now = kpos_c, kext_now = kext_c;
+      bool has2 = false;
+      if (has1) {
+        g.load_data(Ap, Bp);
+        kc_c = min(KT, d1.kext - k1);
+        kpos_c = k1;
+        kext_c = d1.kext;
+        has2 = advance();
+      }
+#pragma unroll
+      for (int st = 0; st < KT / 32; ++st) {  // zeros beyond a ragged chunk's K extent
+        bf8_t af[NS][FM], bfr[NS][FN];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+            af[s][i] = *reinterpret_cast<const bf8_t*>(&As[s * MT * LD + (wm * WM + i * 16 + lr) * LD + 32 * st + 8 * lq]);
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            bfr[s][j] = *reinterpret_cast<const bf8_t*>(&Bs[s * NT * LD + (wn * WN + j * 16 + lr) * LD + 32 * st + 8 * lq]);
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            if (ALIGNED) {
+              lead[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[0][j], lead[i][j], 0, 0, 0);
+              f4_t r = rest[i][j];
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[1][j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[0][j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[2][j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2][i], bfr[0][j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[1][j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[NS - 1][j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[NS - 1][i], bfr[0][j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[2][j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2][i], bfr[1][j], r, 0, 0, 0);
+              rest[i][j] = r;
+            } else {
+              f4_t r = rest[i][j];
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[0][j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[1][j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[0][j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[2][j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2][i], bfr[0][j], r, 0, 0, 0);
+              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[1][j], r, 0, 0, 0);
+              rest[i][j] = r;
+            }
+          }
+      }
+      const int kend = kpos_now + kc_now;
+      if (kend % kSplitWindow == 0 || kend >= kext_now) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              acc[i][j][r] += ALIGNED ? (double)lead[i][j][r] + (double)rest[i][j][r] : (double)rest[i][j][r];
+              lead[i][j][r] = 0.f;
+              rest[i][j][r] = 0.f;
+            }
+      }
+      if (!has1) break;
+      has1 = has2;
+    }
+  }
+  epilogue_f32layout<MT, NT, WM, WN, FM, FN>(pr, w, blk, acc, wm, wn, lr, lq);
+}
+
+// ---------------------------------------------------------------------------------------------
+// configurations and dispatch
+// ---------------------------------------------------------------------------------------------
+static const MixedConfig kF32Configs[] = {
+    {64, 64, 16, 2, 2, "f32_m64n64k16_w2x2"},
+    {128, 64, 16, 2, 2, "f32_m128n64k16_w2x2"},
+    {64, 128, 16, 2, 2, "f32_m64n128k16_w2x2"},
+    {128, 128, 16, 2, 2, "f32_m128n128k16_w2x2"},
+};
+static const MixedConfig kBf16Configs[] = {
+    {64, 64, 32, 2, 2, "bf16s_m64n64k32_w2x2"},
+    {128, 64, 32, 2, 2, "bf16s_m128n64k32_w2x2"},
+    {64, 128, 32, 2, 2, "bf16s_m64n128k32_w2x2"},
+};
+
+int mixed_config_count(int precision) {
+  if (precision == TAMM_PREC_F32) return (int)(sizeof(kF32Configs) / sizeof(kF32Configs[0]));
+  return (int)(sizeof(kBf16Configs) / sizeof(kBf16Configs[0]));
+}
+
+const MixedConfig& mixed_config(int precision, int id) {
+  return precision == TAMM_PREC_F32 ? kF32Configs[id] : kBf16Configs[id];
+}
+
+template <int MT, int NT, int KT, int WGM, int WGN>
+static hipError_t launch_f32(int layout, const ContractParams& p, hipStream_t s) {
+  const dim3 g(p.n_work), b(64 * WGM * WGN);
+  switch (layout) {
+    case 3: hipLaunchKernelGGL((k_contract_f32<MT, NT, KT, WGM, WGN, true, true>), g, b, 0, s, p); break;
+    case 2: hipLaunchKernelGGL((k_contract_f32<MT, NT, KT, WGM, WGN, true, false>), g, b, 0, s, p); break;
+    case 1: hipLaunchKernelGGL((k_contract_f32<MT, NT, KT, WGM, WGN, false, true>), g, b, 0, s, p); break;
+    default: hipLaunchKernelGGL((k_contract_f32<MT, NT, KT, WGM, WGN, false, false>), g, b, 0, s, p); break;
+  }
+  return hipGetLastError();
+}
+
+template <int MT, int NT, int KT, int WGM, int WGN, bool AL>
+static hipError_t launch_bf(int layout, const ContractParams& p, hipStream_t s) {
+  const dim3 g(p.n_work), b(64 * WGM * WGN);
+  switch (layout) {
+    case 3: hipLaunchKernelGGL((k_contract_bf16s<MT, NT, KT, WGM, WGN, AL, true, true>), g, b, 0, s, p); break;
+    case 2: hipLaunchKernelGGL((k_contract_bf16s<MT, NT, KT, WGM, WGN, AL, true, false>), g, b, 0, s, p); break;
+    case 1: hipLaunchKernelGGL((k_contract_bf16s<MT, NT, KT, WGM, WGN, AL, false, true>), g, b, 0, s, p); break;
+    default: hipLaunchKernelGGL((k_contract_bf16s<MT, NT, KT, WGM, WGN, AL, false, false>), g, b, 0, s, p); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_contract_mixed(int precision, int config, int layout, const ContractParams& p, hipStream_t s) {
+  if (p.n_work <= 0) return hipSuccess;
+  if (precision == TAMM_PREC_F32) {
+    switch (config) {
+      case 0: return launch_f32<64, 64, 16, 2, 2>(layout, p, s);
+      case 1: return launch_f32<128, 64, 16, 2, 2>(layout, p, s);
+      case 2: return launch_f32<64, 128, 16, 2, 2>(layout, p, s);
+      case 3: return launch_f32<128, 128, 16, 2, 2>(layout, p, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  const bool al = precision == TAMM_PREC_BF16X4_ALIGNED;
+  switch (config) {
+    case 0: return al ? launch_bf<64, 64, 32, 2, 2, true>(layout, p, s) : launch_bf<64, 64, 32, 2, 2, false>(layout, p, s);
+    case 1: return al ? launch_bf<128, 64, 32, 2, 2, true>(layout, p, s) : launch_bf<128, 64, 32, 2, 2, false>(layout, p, s);
+    case 2: return al ? launch_bf<64, 128, 32, 2, 2, true>(layout, p, s) : launch_bf<64, 128, 32, 2, 2, false>(layout, p, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace tamm

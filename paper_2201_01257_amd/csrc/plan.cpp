@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "host.h"
+#include "mixed.h"
 
 using namespace tamm;
 
@@ -84,6 +85,9 @@ struct tamm_plan {
   std::vector<OutBlockDesc> blocks;
   std::vector<double> block_cost;  // sum of K extents of the surviving pairs of each block
   uint64_t signature = 0;
+  // split-bfloat16 precisions: per stored operand block, the split work description
+  std::vector<PrepBlock> prepA, prepB;
+  int64_t prepA_items = 0, prepB_items = 0;
   // kernel configuration and work decomposition
   int config = -1;
   int k_splits = 1;
@@ -92,7 +96,7 @@ struct tamm_plan {
   tamm_plan_stats stats{};
   // workspace: static layout, then work list, reduce list, partial tiles
   Layout lay;
-  size_t off_work = 0, off_reduce = 0, off_partial = 0, ws_size = 0;
+  size_t off_work = 0, off_reduce = 0, off_partial = 0, off_prepA = 0, off_prepB = 0, off_xA = 0, off_xB = 0, ws_size = 0;
   char* ws = nullptr;
   size_t ws_bytes = 0;
   bool ws_bound = false;
@@ -166,8 +170,9 @@ extern "C" int tamm_plan_create(tamm_tensor* out, const char* out_lbl, const tam
   if (!plan) return fail(TAMM_ERR_ARG, "null output pointer");
   *plan = nullptr;
   if (!out || !lhs || !rhs || !out_lbl || !lhs_lbl || !rhs_lbl) return fail(TAMM_ERR_ARG, "null tensor or label string");
-  if (precision != TAMM_PREC_F64)
-    return fail(TAMM_ERR_UNSUPPORTED, "precision %d is not available in this build", (int)precision);
+  if (precision != TAMM_PREC_F64 && precision != TAMM_PREC_F32 && precision != TAMM_PREC_BF16X3 &&
+      precision != TAMM_PREC_BF16X4_ALIGNED)
+    return fail(TAMM_ERR_ARG, "unknown precision %d", (int)precision);
   const tamm_tensor* ts[3] = {out, lhs, rhs};
   const char* ls[3] = {out_lbl, lhs_lbl, rhs_lbl};
   for (int x = 0; x < 3; ++x) {
@@ -297,6 +302,36 @@ extern "C" int tamm_plan_create(tamm_tensor* out, const char* out_lbl, const tam
   std::vector<int64_t> aM, aK, bK, bN, oM, oN;
   if (!build_tables(ai, p->M, p->K, aM, aK) || !build_tables(bi, p->K, p->N, bK, bN) || !build_tables(oi, p->M, p->N, oM, oN))
     return fail(TAMM_ERR_UNSUPPORTED, "a block has more than 2^31 elements or the offset tables are too large");
+  if (precision == TAMM_PREC_BF16X3 || precision == TAMM_PREC_BF16X4_ALIGNED) {
+    // split work per stored operand block: rows (M for A, N for B) x K windows
+    auto prep_list = [&](const OpInfo& o, const std::vector<int64_t>& rowtab, const std::vector<int64_t>& ktab,
+                         const std::vector<int>& rowgroup, bool kc, std::vector<PrepBlock>& list, int64_t& items) {
+      const tamm_tensor* t = o.t;
+      items = 0;
+      for (size_t b = 0; b < t->block_off.size(); ++b) {
+        const int32_t* tt = &t->block_tiles[b * t->rank];
+        int64_t cls = 0, rows = 1, kext = 1;
+        for (int d = 0; d < t->rank; ++d) {
+          const Label& L = p->labels[o.dim_label[d]];
+          cls += L.cls[tt[d]] * o.cstride[d];
+          const bool is_row = std::find(rowgroup.begin(), rowgroup.end(), o.dim_label[d]) != rowgroup.end();
+          (is_row ? rows : kext) *= L.sp->size[tt[d]];
+        }
+        PrepBlock pb{};
+        pb.off = t->block_off[b];
+        pb.item0 = items;
+        pb.rows = (int32_t)rows;
+        pb.kext = (int32_t)kext;
+        pb.tab_row = (int32_t)rowtab[cls];
+        pb.tab_k = (int32_t)ktab[cls];
+        pb.nwin = (int32_t)((kext + kSplitWindow - 1) / kSplitWindow);
+        items += (kc ? rows : (rows + 63) / 64) * pb.nwin;
+        list.push_back(pb);
+      }
+    };
+    prep_list(ai, aM, aK, p->M, p->a_kc, p->prepA, p->prepA_items);
+    prep_list(bi, bN, bK, p->N, p->b_kc, p->prepB, p->prepB_items);
+  }
   ScreenDesc& sd = p->sd;
   memset(&sd, 0, sizeof(sd));
   sd.a_cls_tabM = pool_push(pool, aM);
@@ -426,9 +461,26 @@ extern "C" int tamm_plan_create(tamm_tensor* out, const char* out_lbl, const tam
   return ok();
 }
 
+// Kernel configuration tables by precision.
+struct TileCfg {
+  int mt, nt, kt, threads;
+  const char* name;
+};
+
+static int cfg_count(int prec) { return prec == TAMM_PREC_F64 ? f64_config_count() : mixed_config_count(prec); }
+
+static TileCfg cfg_get(int prec, int c) {
+  if (prec == TAMM_PREC_F64) {
+    const F64Config& f = f64_config(c);
+    return TileCfg{f.mt, f.nt, f.kt, 64 * f.wgm * f.wgn, f.name};
+  }
+  const MixedConfig& f = mixed_config(prec, c);
+  return TileCfg{f.mt, f.nt, f.kt, 64 * f.wgm * f.wgn, f.name};
+}
+
 // Number of output tiles and padding factor of one configuration.
 static std::pair<int64_t, double> tiles_for(const tamm_plan* p, int c) {
-  const F64Config& f = f64_config(c);
+  const TileCfg f = cfg_get(p->prec, c);
   int64_t n = 0;
   double area = 0, useful = 0;
   for (const auto& b : p->blocks) {
@@ -445,10 +497,10 @@ static std::pair<int64_t, double> tiles_for(const tamm_plan* p, int c) {
 static int default_config(const tamm_plan* p) {
   int best = 0;
   double best_score = -1;
-  for (int c = 0; c < f64_config_count(); ++c) {
+  for (int c = 0; c < cfg_count(p->prec); ++c) {
     auto tw = tiles_for(p, c);
-    const F64Config& f = f64_config(c);
-    if (f.kt != 16 || f.wgm * f.wgn != 4 || f.mt > 128 || f.nt > 128) continue;
+    const TileCfg f = cfg_get(p->prec, c);
+    if ((p->prec == TAMM_PREC_F64 && f.kt != 16) || f.threads != 256 || f.mt > 128 || f.nt > 128) continue;
     double score = (double)f.mt * f.nt / tw.second;
     if (tw.first < 512) score *= (double)tw.first / 512.0;
     if (score > best_score) {
@@ -462,11 +514,11 @@ static int default_config(const tamm_plan* p) {
 // Work decomposition for one kernel configuration: macro-tiles of every stored output block,
 // heaviest first (longest-processing-time order), with the K splits of a tile adjacent.
 static int configure_work(tamm_plan* p, int config, int k_splits) {
-  const int ncfg = f64_config_count();
+  const int ncfg = cfg_count(p->prec);
   const int64_t nob = (int64_t)p->blocks.size();
   if (config < 0) config = default_config(p);
   if (config >= ncfg) return fail(TAMM_ERR_ARG, "kernel configuration %d does not exist (%d available)", config, ncfg);
-  const F64Config& f = f64_config(config);
+  const TileCfg f = cfg_get(p->prec, config);
   const int64_t ntiles = tiles_for(p, config).first;
   if (k_splits <= 0) {
     k_splits = 1;
@@ -514,6 +566,16 @@ static int configure_work(tamm_plan* p, int config, int k_splits) {
   off = align256(off + p->reduce.size() * sizeof(ReduceItem));
   p->off_partial = off;
   if (k_splits > 1) off = align256(off + tiles.size() * (size_t)k_splits * f.mt * f.nt * sizeof(double));
+  if (p->prec == TAMM_PREC_BF16X3 || p->prec == TAMM_PREC_BF16X4_ALIGNED) {
+    p->off_prepA = off;
+    off = align256(off + p->prepA.size() * sizeof(PrepBlock));
+    p->off_prepB = off;
+    off = align256(off + p->prepB.size() * sizeof(PrepBlock));
+    p->off_xA = off;
+    off = align256(off + (size_t)p->A->numel * sizeof(uint64_t));
+    p->off_xB = off;
+    off = align256(off + (size_t)p->B->numel * sizeof(uint64_t));
+  }
   p->ws_size = std::max<size_t>(off, 256);
   p->ws_bound = false;
   p->screened = false;
@@ -536,6 +598,8 @@ static int bind_plan(tamm_plan* p, void* dev_ptr, size_t bytes) {
   if (!p->work.empty()) HIP_TRY(hipMemcpy(ws + p->off_work, p->work.data(), p->work.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
   if (!p->reduce.empty())
     HIP_TRY(hipMemcpy(ws + p->off_reduce, p->reduce.data(), p->reduce.size() * sizeof(ReduceItem), hipMemcpyHostToDevice));
+  if (!p->prepA.empty()) HIP_TRY(hipMemcpy(ws + p->off_prepA, p->prepA.data(), p->prepA.size() * sizeof(PrepBlock), hipMemcpyHostToDevice));
+  if (!p->prepB.empty()) HIP_TRY(hipMemcpy(ws + p->off_prepB, p->prepB.data(), p->prepB.size() * sizeof(PrepBlock), hipMemcpyHostToDevice));
   p->ws = ws;
   p->ws_bytes = bytes;
   p->ws_bound = true;
@@ -558,13 +622,13 @@ extern "C" int tamm_plan_stats_get(const tamm_plan* p, tamm_plan_stats* s) {
 
 extern "C" int tamm_plan_config_count(const tamm_plan* p, int32_t* count) {
   if (!p || !count) return fail(TAMM_ERR_ARG, "null argument");
-  *count = f64_config_count();
+  *count = cfg_count(p->prec);
   return ok();
 }
 
 extern "C" int tamm_plan_set_config(tamm_plan* p, int32_t config, int32_t k_splits) {
   if (!p) return fail(TAMM_ERR_ARG, "null plan");
-  if (config < 0 || config >= f64_config_count()) return fail(TAMM_ERR_ARG, "configuration %d does not exist", config);
+  if (config < 0 || config >= cfg_count(p->prec)) return fail(TAMM_ERR_ARG, "configuration %d does not exist", config);
   if (k_splits < 0 || k_splits > 64) return fail(TAMM_ERR_ARG, "k_splits must be in [0, 64]");
   const int rc = configure_work(p, config, k_splits);
   if (rc != TAMM_OK) return rc;
@@ -572,8 +636,9 @@ extern "C" int tamm_plan_set_config(tamm_plan* p, int32_t config, int32_t k_spli
 }
 
 extern "C" const char* tamm_config_name(int32_t precision, int32_t config) {
-  if (precision != TAMM_PREC_F64 || config < 0 || config >= f64_config_count()) return "";
-  return f64_config(config).name;
+  if (precision < TAMM_PREC_F64 || precision > TAMM_PREC_BF16X4_ALIGNED) return "";
+  if (config < 0 || config >= cfg_count(precision)) return "";
+  return cfg_get(precision, config).name;
 }
 
 static bool overlaps(const tamm_tensor* a, const tamm_tensor* b) {
@@ -617,9 +682,35 @@ static int contract_launch(tamm_plan* p, double alpha, double beta, hipStream_t 
   cp.work = (const WorkItem*)(p->ws + p->off_work);
   cp.next_item = nullptr;
   cp.n_work = (int32_t)p->work.size();
-  HIP_TRY(launch_contract_f64(p->config, 2 * (p->a_kc ? 1 : 0) + (p->b_kc ? 1 : 0), cp, 0, s));
+  const int layout = 2 * (p->a_kc ? 1 : 0) + (p->b_kc ? 1 : 0);
+  if (p->prec == TAMM_PREC_F64) {
+    HIP_TRY(launch_contract_f64(p->config, layout, cp, 0, s));
+  } else {
+    if (p->prec != TAMM_PREC_F32) {
+      // operand split into packed bfloat16 slices, then the contraction reads the split copies
+      PrepParams pa{};
+      pa.x = p->A->dev;
+      pa.out = (uint64_t*)(p->ws + p->off_xA);
+      pa.blocks = (const PrepBlock*)(p->ws + p->off_prepA);
+      pa.pool = (const int32_t*)(p->ws + p->lay.pool);
+      pa.n_items = p->prepA_items;
+      pa.n_blocks = (int32_t)p->prepA.size();
+      pa.aligned = p->prec == TAMM_PREC_BF16X4_ALIGNED ? 1 : 0;
+      HIP_TRY(launch_prep_split(pa, !p->a_kc, s));
+      PrepParams pbp = pa;
+      pbp.x = p->B->dev;
+      pbp.out = (uint64_t*)(p->ws + p->off_xB);
+      pbp.blocks = (const PrepBlock*)(p->ws + p->off_prepB);
+      pbp.n_items = p->prepB_items;
+      pbp.n_blocks = (int32_t)p->prepB.size();
+      HIP_TRY(launch_prep_split(pbp, !p->b_kc, s));
+      cp.single.A = (const double*)(p->ws + p->off_xA);
+      cp.single.B = (const double*)(p->ws + p->off_xB);
+    }
+    HIP_TRY(launch_contract_mixed(p->prec, p->config, layout, cp, s));
+  }
   if (p->k_splits > 1) {
-    const F64Config& f = f64_config(p->config);
+    const TileCfg f = cfg_get(p->prec, p->config);
     ReduceParams r{};
     r.single = cp.single;
     r.probs = nullptr;
@@ -721,7 +812,7 @@ extern "C" int tamm_plan_autotune_workspace_size(const tamm_plan* p, size_t* byt
   if (!p || !bytes) return fail(TAMM_ERR_ARG, "null argument");
   tamm_plan tmp = *p;
   size_t mx = 0;
-  for (int c = 0; c < f64_config_count(); ++c)
+  for (int c = 0; c < cfg_count(p->prec); ++c)
     for (int ks : {1, 2, 4, 8}) {
       if (configure_work(&tmp, c, ks) != TAMM_OK) continue;
       mx = std::max(mx, tmp.ws_size);
@@ -743,7 +834,7 @@ extern "C" int tamm_plan_autotune(tamm_plan* p, void* workspace, size_t bytes, v
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     const int64_t ntiles_max = tiles_for(p, 0).first;
-    for (int c = 0; c < f64_config_count(); ++c) {
+    for (int c = 0; c < cfg_count(p->prec); ++c) {
       const int64_t nt = tiles_for(p, c).first;
       for (int ks : {1, 2, 4, 8}) {
         if (ks > 1 && nt * ks > 4 * std::max<int64_t>(ntiles_max, 2048)) continue;

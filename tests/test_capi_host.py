@@ -115,8 +115,10 @@ def test_error_codes():
     assert status_of(lambda: tm.Plan(R, "ab1j", V, "abcd", T, "cdij", bind=False)) == "TAMM_ERR_LABEL"
     # label d bound to virtual (V) and to occupied (T) spaces
     assert status_of(lambda: tm.Plan(R, "abij", V, "abcd", T, "cidj", bind=False)) == "TAMM_ERR_LABEL"
-    assert status_of(lambda: tm.Plan(R, "abij", V, "abcd", T, "cdij", precision="bf16x3_exact", bind=False)) in (
-        "TAMM_ERR_UNSUPPORTED", "TAMM_OK")
+    for prec in ("f32", "bf16x3", "bf16x4_aligned"):
+        tm.Plan(R, "abij", V, "abcd", T, "cdij", precision=prec, bind=False)  # every precision plans
+    h0 = ctypes.c_void_p()
+    assert lib.tamm_plan_create(R._h, b"abij", V._h, b"abcd", T._h, b"cdij", 7, ctypes.byref(h0)) == -1  # bad precision
     # Fig. 4 as printed: B(i,l) with B declared over (tK, tN) binds i to two spaces
     tM = tm.Space.explicit([10, 20])
     tK = tm.Space.fixed(20, 5)
