@@ -1,0 +1,221 @@
+// Device helpers shared by the contraction kernels: bounds-checked buffer loads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace tamm {
+
+// Byte offset that lies outside every block range used with the buffer loads below: a raw
+// buffer load whose offset is at or beyond the resource's size returns zero (no memory access),
+// which is how padding rows, columns and k positions read as zeros without branches.
+constexpr uint32_t kOutOfRange = 0x40000000u;
+// Largest block the gathers address through one buffer resource (bytes, exclusive).
+constexpr int64_t kMaxBlockBytes = (int64_t)kOutOfRange;
+
+// Loads through explicit address spaces: per-lane table reads as global loads (not flat), and
+// wave-uniform descriptor reads as scalar loads from the constant address space (the descriptors
+// are never written while a kernel runs).
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)(p);
+}
+template <typename T>
+__device__ __forceinline__ T sload(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized descriptor");
+  const __attribute__((address_space(4))) uint32_t* q = (const __attribute__((address_space(4))) uint32_t*)(p);
+  uint32_t w[sizeof(T) / 4];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = q[i];
+  return __builtin_bit_cast(T, w);
+}
+
+// Values the whole wave agrees on, moved to scalar registers (descriptors loaded through
+// pointers are not provably uniform to the compiler; a buffer resource in vector registers would
+// need a per-lane loop around every load).
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t wave_uniform(int64_t x) {
+  const uint64_t v = (uint64_t)x;
+  return (int64_t)(((uint64_t)wave_uniform((uint32_t)(v >> 32)) << 32) | wave_uniform((uint32_t)v));
+}
+template <typename T>
+__device__ __forceinline__ T* wave_uniform(T* p) {
+  return reinterpret_cast<T*>(wave_uniform((int64_t)reinterpret_cast<uintptr_t>(p)));
+}
+__device__ __forceinline__ PairDesc wave_uniform(const PairDesc& d) {
+  PairDesc u;
+  u.a_off = wave_uniform(d.a_off);
+  u.b_off = wave_uniform(d.b_off);
+  u.kext = wave_uniform(d.kext);
+  u.a_tabM = wave_uniform(d.a_tabM);
+  u.a_tabK = wave_uniform(d.a_tabK);
+  u.b_tabK = wave_uniform(d.b_tabK);
+  u.b_tabN = wave_uniform(d.b_tabN);
+  u.kt = wave_uniform(d.kt);
+  return u;
+}
+
+__device__ __forceinline__ double wave_uniform(double x) {
+  return __builtin_bit_cast(double, wave_uniform(__builtin_bit_cast(int64_t, x)));
+}
+__device__ __forceinline__ ProblemDesc wave_uniform(const ProblemDesc& d) {
+  ProblemDesc u;
+  u.A = wave_uniform(d.A);
+  u.B = wave_uniform(d.B);
+  u.C = wave_uniform(d.C);
+  u.blocks = wave_uniform(d.blocks);
+  u.pairs = wave_uniform(d.pairs);
+  u.counts = wave_uniform(d.counts);
+  u.pool = wave_uniform(d.pool);
+  u.partial = wave_uniform(d.partial);
+  u.alpha = wave_uniform(d.alpha);
+  u.beta = wave_uniform(d.beta);
+  u.k_splits = wave_uniform(d.k_splits);
+  u.a_kc = wave_uniform(d.a_kc);
+  u.b_kc = wave_uniform(d.b_kc);
+  u.pad = 0;
+  return u;
+}
+__device__ __forceinline__ WorkItem wave_uniform(const WorkItem& w) {
+  return WorkItem{wave_uniform(w.prob), wave_uniform(w.ob), wave_uniform(w.m0), wave_uniform(w.n0), wave_uniform(w.split),
+                  wave_uniform(w.tile)};
+}
+__device__ __forceinline__ OutBlockDesc wave_uniform(const OutBlockDesc& b) {
+  OutBlockDesc u;
+  u.c_off = wave_uniform(b.c_off);
+  u.mext = wave_uniform(b.mext);
+  u.next = wave_uniform(b.next);
+  u.c_tabM = wave_uniform(b.c_tabM);
+  u.c_tabN = wave_uniform(b.c_tabN);
+  u.a_tbase = wave_uniform(b.a_tbase);
+  u.b_tbase = wave_uniform(b.b_tbase);
+  u.a_cbase = wave_uniform(b.a_cbase);
+  u.b_cbase = wave_uniform(b.b_cbase);
+  u.pair_base = wave_uniform(b.pair_base);
+  u.pad = 0;
+  return u;
+}
+
+// Raw buffer resource over [base, base + bytes) (gfx9 buffer descriptor, 32-bit data format word).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(wave_uniform(base)), (short)0, (int)wave_uniform(bytes),
+                                           0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T buffer_load8(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  static_assert(sizeof(T) == 8, "8-byte element");
+  return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
+}
+
+}  // namespace tamm
+
+namespace tamm {
+
+// Per-thread gather state of one contraction workgroup (shared by the float64 and mixed kernels).
+//
+// A chunk of A is MT rows x KT summed indices, of B NT rows x KT.  With a k-contiguous operand
+// (its stride-1 label is summed) the lanes run along k: a thread owns one k and AE (BE) rows;
+// otherwise the lanes run along the rows: a thread owns one row and AE (BE) k positions.
+// Element e of a thread lands in LDS at row X_r0 + e*X_DR, k X_k0 + e*X_DK.
+//
+// Everything is branch-free: table entries are fetched at clamped (always valid) positions and
+// their validity is kept aside; the data load of an invalid element uses kOutOfRange as its byte
+// offset and the buffer hardware returns zero.  Table entries of the chunk after next are
+// fetched while the data of the next chunk is in flight, so no dependent table->data chain
+// sits in front of the MFMAs.
+template <int MT, int NT, int KT, int NTHR, bool A_KC, bool B_KC, typename T>
+struct Gather {
+  static constexpr int AE = MT * KT / NTHR;
+  static constexpr int BE = NT * KT / NTHR;
+  static constexpr int A_NR = A_KC ? AE : 1, A_NK = A_KC ? 1 : AE;
+  static constexpr int B_NR = B_KC ? BE : 1, B_NK = B_KC ? 1 : BE;
+  static constexpr int A_DR = A_KC ? NTHR / KT : 0, A_DK = A_KC ? 0 : NTHR / MT;
+  static constexpr int B_DR = B_KC ? NTHR / KT : 0, B_DK = B_KC ? 0 : NTHR / NT;
+  static_assert(!A_KC || (NTHR % KT == 0 && MT % (NTHR / KT) == 0), "k-contiguous A gather mapping");
+  static_assert(!B_KC || (NTHR % KT == 0 && NT % (NTHR / KT) == 0), "k-contiguous B gather mapping");
+  static_assert(A_KC || (NTHR % MT == 0 && KT % (NTHR / MT) == 0), "m-contiguous A gather mapping");
+  static_assert(B_KC || (NTHR % NT == 0 && KT % (NTHR / NT) == 0), "n-contiguous B gather mapping");
+  static_assert(AE <= 32 && BE <= 32, "validity masks hold 32 elements");
+
+  int a_k0, a_r0, b_k0, b_r0;
+  const T* a_base;                        // current pair's operand blocks
+  const T* b_base;
+  uint32_t a_bytes, b_bytes;
+  int a_rt[A_NR], b_rt[B_NR];             // row table entries (elements)
+  int a_kt[A_NK], b_kt[B_NK];             // k table entries (elements)
+  uint32_t a_rok, b_rok, a_kok, b_kok;    // validity bits
+  T ra[AE], rb[BE];
+
+  __device__ void init(int tid) {
+    a_k0 = A_KC ? tid % KT : tid / MT;
+    a_r0 = A_KC ? tid / KT : tid % MT;
+    b_k0 = B_KC ? tid % KT : tid / NT;
+    b_r0 = B_KC ? tid / KT : tid % NT;
+  }
+  __device__ void setup_pair(const PairDesc& d, const int32_t* pool, const T* A, const T* B, int m0, int n0, int mext,
+                             int next) {
+    a_base = A + d.a_off;
+    b_base = B + d.b_off;
+    a_bytes = (uint32_t)((int64_t)mext * d.kext * 8);
+    b_bytes = (uint32_t)((int64_t)next * d.kext * 8);
+    a_rok = 0;
+    b_rok = 0;
+#pragma unroll
+    for (int e = 0; e < A_NR; ++e) {
+      const int m = m0 + a_r0 + e * A_DR;
+      a_rt[e] = gload(pool + d.a_tabM + min(m, mext - 1));
+      a_rok |= (m < mext ? 1u : 0u) << e;
+    }
+#pragma unroll
+    for (int e = 0; e < B_NR; ++e) {
+      const int n = n0 + b_r0 + e * B_DR;
+      b_rt[e] = gload(pool + d.b_tabN + min(n, next - 1));
+      b_rok |= (n < next ? 1u : 0u) << e;
+    }
+  }
+  __device__ void load_tables(const PairDesc& d, const int32_t* pool, int kbase) {
+    a_kok = 0;
+    b_kok = 0;
+#pragma unroll
+    for (int e = 0; e < A_NK; ++e) {
+      const int k = kbase + a_k0 + e * A_DK;
+      a_kt[e] = gload(pool + d.a_tabK + min(k, d.kext - 1));
+      a_kok |= (k < d.kext ? 1u : 0u) << e;
+    }
+#pragma unroll
+    for (int e = 0; e < B_NK; ++e) {
+      const int k = kbase + b_k0 + e * B_DK;
+      b_kt[e] = gload(pool + d.b_tabK + min(k, d.kext - 1));
+      b_kok |= (k < d.kext ? 1u : 0u) << e;
+    }
+  }
+  __device__ void load_data() {
+    // resources built here from wave-uniform values, so that they live in scalar registers
+    const __amdgpu_buffer_rsrc_t a_rsrc = block_rsrc(a_base, a_bytes);
+    const __amdgpu_buffer_rsrc_t b_rsrc = block_rsrc(b_base, b_bytes);
+#pragma unroll
+    for (int e = 0; e < AE; ++e) {
+      const int er = A_KC ? e : 0, ek = A_KC ? 0 : e;
+      const bool ok = ((a_rok >> er) & (a_kok >> ek) & 1u) != 0;
+      const uint32_t off = ok ? (uint32_t)(a_rt[er] + a_kt[ek]) * 8u : kOutOfRange;
+      ra[e] = buffer_load8<T>(a_rsrc, off);
+    }
+#pragma unroll
+    for (int e = 0; e < BE; ++e) {
+      const int er = B_KC ? e : 0, ek = B_KC ? 0 : e;
+      const bool ok = ((b_rok >> er) & (b_kok >> ek) & 1u) != 0;
+      const uint32_t off = ok ? (uint32_t)(b_rt[er] + b_kt[ek]) * 8u : kOutOfRange;
+      rb[e] = buffer_load8<T>(b_rsrc, off);
+    }
+  }
+  __device__ int a_lds_row(int e) const { return a_r0 + e * A_DR; }
+  __device__ int a_lds_k(int e) const { return a_k0 + e * A_DK; }
+  __device__ int b_lds_row(int e) const { return b_r0 + e * B_DR; }
+  __device__ int b_lds_k(int e) const { return b_k0 + e * B_DK; }
+};
+
+}  // namespace tamm

@@ -3,6 +3,7 @@
 // reduction and the orbital-energy denominator update.
 #include <hip/hip_runtime.h>
 
+#include "device_util.h"
 #include "internal.h"
 
 namespace tamm {
@@ -101,21 +102,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f64(ContractParams 
   constexpr int WM = MT / WGM, WN = NT / WGN;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int LD = KT + 2;  // LDS row stride in doubles
-  constexpr int AE = MT * KT / NTHR;
-  constexpr int BE = NT * KT / NTHR;
   static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile must be a multiple of 16");
   static_assert(KT % 4 == 0, "KT multiple of 4");
-  static_assert(!A_KC || (NTHR % KT == 0 && MT % (NTHR / KT) == 0), "k-contiguous A gather mapping");
-  static_assert(!B_KC || (NTHR % KT == 0 && NT % (NTHR / KT) == 0), "k-contiguous B gather mapping");
-  static_assert(A_KC || (NTHR % MT == 0 && KT % (NTHR / MT) == 0), "m-contiguous A gather mapping");
-  static_assert(B_KC || (NTHR % NT == 0 && KT % (NTHR / NT) == 0), "n-contiguous B gather mapping");
-  // element e of this thread's share of a chunk: row X_r0 + e*X_dr, k X_k0 + e*X_dk.  With a
-  // k-contiguous operand every element shares one k (and has its own row); otherwise every
-  // element shares one row (and has its own k).
-  constexpr int A_NR = A_KC ? AE : 1, A_NK = A_KC ? 1 : AE;
-  constexpr int B_NR = B_KC ? BE : 1, B_NK = B_KC ? 1 : BE;
-  constexpr int A_DR = A_KC ? NTHR / KT : 0, A_DK = A_KC ? 0 : NTHR / MT;
-  constexpr int B_DR = B_KC ? NTHR / KT : 0, B_DK = B_KC ? 0 : NTHR / NT;
+  using G = Gather<MT, NT, KT, NTHR, A_KC, B_KC, double>;
   __shared__ double As[MT * LD];
   __shared__ double Bs[NT * LD];
   __shared__ int s_next;
@@ -123,30 +112,27 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f64(ContractParams 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
   const int lr = lane & 15, lq = lane >> 4;
-  const int a_k0 = A_KC ? tid % KT : tid / MT;
-  const int a_r0 = A_KC ? tid / KT : tid % MT;
-  const int b_k0 = B_KC ? tid % KT : tid / NT;
-  const int b_r0 = B_KC ? tid / KT : tid % NT;
+  G g;
+  g.init(tid);
 
   int item = blockIdx.x;
   while (item < P.n_work) {
-    const WorkItem w = P.work[item];
-    const ProblemDesc& pr = P.probs ? P.probs[w.prob] : P.single;
-    const OutBlockDesc blk = pr.blocks[w.ob];
+    // work-item descriptors are the same for the whole wave: keep them in scalar registers
+    const WorkItem w = wave_uniform(sload(P.work + item));
+    const ProblemDesc pr = wave_uniform(P.probs ? sload(P.probs + w.prob) : P.single);
+    const OutBlockDesc blk = wave_uniform(sload(pr.blocks + w.ob));
     const int32_t* __restrict__ pool = pr.pool;
-    const double* __restrict__ Ag = pr.A;
-    const double* __restrict__ Bg = pr.B;
     const PairDesc* __restrict__ pairs = pr.pairs + blk.pair_base;
-    const int cnt = pr.counts[w.ob];
+    const int cnt = wave_uniform(gload(pr.counts + w.ob));
     int pb = 0, pe = cnt;
     if (pr.k_splits > 1) {
       pb = (int)(((int64_t)cnt * w.split) / pr.k_splits);
       pe = (int)(((int64_t)cnt * (w.split + 1)) / pr.k_splits);
     }
-
-    int64_t a_row[A_NR], b_row[B_NR];  // element offset of the row (incl. block offset), -1 if out of range
-    int a_kof[A_NK], b_kof[B_NK];      // K-table entry of the k, -1 past the pair's K extent
-    double ra[AE], rb[BE];
+    // MFMA blocks of this wave that hold at least one valid row / column (uniform per wave)
+    const int fm_valid = wave_uniform(min(FM, max(0, (blk.mext - w.m0 - wm * WM + 15) >> 4)));
+    const int fn_valid = wave_uniform(min(FN, max(0, (blk.next - w.n0 - wn * WN + 15) >> 4)));
+    const bool full = fm_valid == FM && fn_valid == FN;
 
     d4_t acc[FM][FN];
 #pragma unroll
@@ -154,95 +140,41 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f64(ContractParams 
 #pragma unroll
       for (int j = 0; j < FN; ++j) acc[i][j] = (d4_t){0.0, 0.0, 0.0, 0.0};
 
-    auto setup_pair = [&](const PairDesc& d) {
-#pragma unroll
-      for (int e = 0; e < A_NR; ++e) {
-        const int m = w.m0 + a_r0 + e * A_DR;
-        a_row[e] = (m < blk.mext) ? d.a_off + pool[d.a_tabM + m] : -1;
-      }
-#pragma unroll
-      for (int e = 0; e < B_NR; ++e) {
-        const int n = w.n0 + b_r0 + e * B_DR;
-        b_row[e] = (n < blk.next) ? d.b_off + pool[d.b_tabN + n] : -1;
-      }
-    };
-    auto load_kofs = [&](const PairDesc& d, int kbase) {
-#pragma unroll
-      for (int e = 0; e < A_NK; ++e) {
-        const int k = kbase + a_k0 + e * A_DK;
-        a_kof[e] = (k < d.kext) ? pool[d.a_tabK + k] : -1;
-      }
-#pragma unroll
-      for (int e = 0; e < B_NK; ++e) {
-        const int k = kbase + b_k0 + e * B_DK;
-        b_kof[e] = (k < d.kext) ? pool[d.b_tabK + k] : -1;
-      }
-    };
-    auto load_data = [&]() {
-#pragma unroll
-      for (int e = 0; e < AE; ++e) {
-        const int64_t r = a_row[A_KC ? e : 0];
-        const int k = a_kof[A_KC ? 0 : e];
-        ra[e] = (r >= 0 && k >= 0) ? Ag[r + k] : 0.0;
-      }
-#pragma unroll
-      for (int e = 0; e < BE; ++e) {
-        const int64_t r = b_row[B_KC ? e : 0];
-        const int k = b_kof[B_KC ? 0 : e];
-        rb[e] = (r >= 0 && k >= 0) ? Bg[r + k] : 0.0;
-      }
-    };
-
     if (pb < pe) {
-      // chunk cursors: c = next into LDS, n1 = data in flight, n2 = tables in flight
-      PairDesc d1 = pairs[pb];
+      // chunk cursors: c = next into LDS, n1 = data in flight, n2 = table entries in flight
+      PairDesc d1 = wave_uniform(sload(pairs + pb));
       int p1 = pb, k1 = 0;
-      setup_pair(d1);
-      load_kofs(d1, 0);
-      load_data();
-      int kc_c = min(KT, d1.kext);
-      bool has1 = true;
-      k1 += KT;
-      if (k1 >= d1.kext) {
-        ++p1;
-        k1 = 0;
-        if (p1 < pe) {
-          d1 = pairs[p1];
-          setup_pair(d1);
-        } else {
-          has1 = false;
+      g.setup_pair(d1, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next);
+      g.load_tables(d1, pool, 0);
+      g.load_data();
+      auto advance = [&]() {
+        k1 += KT;
+        if (k1 >= d1.kext) {
+          ++p1;
+          k1 = 0;
+          if (p1 >= pe) return false;
+          d1 = wave_uniform(sload(pairs + p1));
+          g.setup_pair(d1, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next);
         }
-      }
-      if (has1) load_kofs(d1, k1);
+        g.load_tables(d1, pool, k1);
+        return true;
+      };
+      bool has1 = advance();
       while (true) {
         __syncthreads();  // the previous chunk's LDS reads are complete
 #pragma unroll
-        for (int e = 0; e < AE; ++e) As[(a_r0 + e * A_DR) * LD + a_k0 + e * A_DK] = ra[e];
+        for (int e = 0; e < G::AE; ++e) As[g.a_lds_row(e) * LD + g.a_lds_k(e)] = g.ra[e];
 #pragma unroll
-        for (int e = 0; e < BE; ++e) Bs[(b_r0 + e * B_DR) * LD + b_k0 + e * B_DK] = rb[e];
+        for (int e = 0; e < G::BE; ++e) Bs[g.b_lds_row(e) * LD + g.b_lds_k(e)] = g.rb[e];
         __syncthreads();
-        const int kc_now = kc_c;
         bool has2 = false;
         if (has1) {
-          load_data();  // chunk n1 (its table entries arrived during the previous MFMA phase)
-          kc_c = min(KT, d1.kext - k1);
-          k1 += KT;
-          has2 = true;
-          if (k1 >= d1.kext) {
-            ++p1;
-            k1 = 0;
-            if (p1 < pe) {
-              d1 = pairs[p1];
-              setup_pair(d1);
-            } else {
-              has2 = false;
-            }
-          }
-          if (has2) load_kofs(d1, k1);
+          g.load_data();  // chunk n1 (its table entries arrived during the previous MFMA phase)
+          has2 = advance();
         }
-        // All KT/4 k-steps run, fully unrolled so that the LDS reads of step s+1 overlap the
-        // MFMAs of step s; a ragged last chunk of a pair holds zeros beyond its K extent.
-        (void)kc_now;
+        // All KT/4 k-steps run, unrolled so that the LDS reads of step s+1 overlap the MFMAs of
+        // step s; a ragged last chunk of a pair holds zeros beyond its K extent.  MFMA blocks
+        // wholly outside the output block are skipped.
 #pragma unroll
         for (int s = 0; s < KT / 4; ++s) {
           const int k = 4 * s + lq;
@@ -251,10 +183,19 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f64(ContractParams 
           for (int i = 0; i < FM; ++i) af[i] = As[(wm * WM + i * 16 + lr) * LD + k];
 #pragma unroll
           for (int j = 0; j < FN; ++j) bf[j] = Bs[(wn * WN + j * 16 + lr) * LD + k];
+          if (full) {
 #pragma unroll
-          for (int i = 0; i < FM; ++i)
+            for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+              for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+          } else {
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+              for (int j = 0; j < FN; ++j)
+                if (i < fm_valid && j < fn_valid)
+                  acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+          }
         }
         if (!has1) break;
         has1 = has2;

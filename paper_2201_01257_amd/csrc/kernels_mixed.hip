@@ -19,6 +19,7 @@
 //           its own accumulator, and only the small residual products see float32 rounding.
 #include <hip/hip_runtime.h>
 
+#include "device_util.h"
 #include "internal.h"
 #include "mixed.h"
 
@@ -147,76 +148,6 @@ hipError_t launch_prep_split(const PrepParams& p, bool rows_along_lanes, hipStre
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------------------------
-// Shared gather pipeline of the mixed kernels (same structure as the float64 kernel: offset-table
-// entries one chunk ahead, data one chunk ahead, MFMAs on the chunk in LDS).
-// ---------------------------------------------------------------------------------------------
-template <int MT, int NT, int KT, int NTHR, bool A_KC, bool B_KC, typename T>
-struct Gather {
-  static constexpr int AE = MT * KT / NTHR;
-  static constexpr int BE = NT * KT / NTHR;
-  static constexpr int A_NR = A_KC ? AE : 1, A_NK = A_KC ? 1 : AE;
-  static constexpr int B_NR = B_KC ? BE : 1, B_NK = B_KC ? 1 : BE;
-  static constexpr int A_DR = A_KC ? NTHR / KT : 0, A_DK = A_KC ? 0 : NTHR / MT;
-  static constexpr int B_DR = B_KC ? NTHR / KT : 0, B_DK = B_KC ? 0 : NTHR / NT;
-  static_assert(!A_KC || (NTHR % KT == 0 && MT % (NTHR / KT) == 0), "k-contiguous A gather mapping");
-  static_assert(!B_KC || (NTHR % KT == 0 && NT % (NTHR / KT) == 0), "k-contiguous B gather mapping");
-  static_assert(A_KC || (NTHR % MT == 0 && KT % (NTHR / MT) == 0), "m-contiguous A gather mapping");
-  static_assert(B_KC || (NTHR % NT == 0 && KT % (NTHR / NT) == 0), "n-contiguous B gather mapping");
-  int a_k0, a_r0, b_k0, b_r0;
-  int64_t a_row[A_NR], b_row[B_NR];
-  int a_kof[A_NK], b_kof[B_NK];
-  T ra[AE], rb[BE];
-  __device__ void init(int tid) {
-    a_k0 = A_KC ? tid % KT : tid / MT;
-    a_r0 = A_KC ? tid / KT : tid % MT;
-    b_k0 = B_KC ? tid % KT : tid / NT;
-    b_r0 = B_KC ? tid / KT : tid % NT;
-  }
-  __device__ void setup_pair(const PairDesc& d, const int32_t* pool, int m0, int n0, int mext, int next) {
-#pragma unroll
-    for (int e = 0; e < A_NR; ++e) {
-      const int m = m0 + a_r0 + e * A_DR;
-      a_row[e] = (m < mext) ? d.a_off + pool[d.a_tabM + m] : -1;
-    }
-#pragma unroll
-    for (int e = 0; e < B_NR; ++e) {
-      const int n = n0 + b_r0 + e * B_DR;
-      b_row[e] = (n < next) ? d.b_off + pool[d.b_tabN + n] : -1;
-    }
-  }
-  __device__ void load_kofs(const PairDesc& d, const int32_t* pool, int kbase) {
-#pragma unroll
-    for (int e = 0; e < A_NK; ++e) {
-      const int k = kbase + a_k0 + e * A_DK;
-      a_kof[e] = (k < d.kext) ? pool[d.a_tabK + k] : -1;
-    }
-#pragma unroll
-    for (int e = 0; e < B_NK; ++e) {
-      const int k = kbase + b_k0 + e * B_DK;
-      b_kof[e] = (k < d.kext) ? pool[d.b_tabK + k] : -1;
-    }
-  }
-  __device__ void load_data(const T* Ag, const T* Bg) {
-#pragma unroll
-    for (int e = 0; e < AE; ++e) {
-      const int64_t r = a_row[A_KC ? e : 0];
-      const int k = a_kof[A_KC ? 0 : e];
-      ra[e] = (r >= 0 && k >= 0) ? Ag[r + k] : T(0);
-    }
-#pragma unroll
-    for (int e = 0; e < BE; ++e) {
-      const int64_t r = b_row[B_KC ? e : 0];
-      const int k = b_kof[B_KC ? 0 : e];
-      rb[e] = (r >= 0 && k >= 0) ? Bg[r + k] : T(0);
-    }
-  }
-  __device__ int a_lds_row(int e) const { return a_r0 + e * A_DR; }
-  __device__ int a_lds_k(int e) const { return a_k0 + e * A_DK; }
-  __device__ int b_lds_row(int e) const { return b_r0 + e * B_DR; }
-  __device__ int b_lds_k(int e) const { return b_k0 + e * B_DK; }
-};
-
 // Epilogue shared by the mixed kernels: float64 accumulators in the float32 MFMA layout (D[m][n]
 // in lane n + 16*(m/4), register m%4).
 template <int MT, int NT, int WM, int WN, int FM, int FN>
@@ -268,12 +199,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
   const int wm = wave % WGM, wn = wave / WGM, lr = lane & 15, lq = lane >> 4;
   const int item = blockIdx.x;
   if (item >= P.n_work) return;
-  const WorkItem w = P.work[item];
-  const ProblemDesc& pr = P.probs ? P.probs[w.prob] : P.single;
-  const OutBlockDesc blk = pr.blocks[w.ob];
+  const WorkItem w = wave_uniform(sload(P.work + item));
+  const ProblemDesc pr = wave_uniform(P.probs ? sload(P.probs + w.prob) : P.single);
+  const OutBlockDesc blk = wave_uniform(sload(pr.blocks + w.ob));
   const int32_t* __restrict__ pool = pr.pool;
   const PairDesc* __restrict__ pairs = pr.pairs + blk.pair_base;
-  const int cnt = pr.counts[w.ob];
+  const int cnt = wave_uniform(gload(pr.counts + w.ob));
   int pb = 0, pe = cnt;
   if (pr.k_splits > 1) {
     pb = (int)(((int64_t)cnt * w.split) / pr.k_splits);
@@ -291,11 +222,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
       part[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
     }
   if (pb < pe) {
-    PairDesc d1 = pairs[pb];
+    PairDesc d1 = wave_uniform(sload(pairs + pb));
     int p1 = pb, k1 = 0;
-    g.setup_pair(d1, pool, w.m0, w.n0, blk.mext, blk.next);
-    g.load_kofs(d1, pool, 0);
-    g.load_data(pr.A, pr.B);
+    g.setup_pair(d1, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next);
+    g.load_tables(d1, pool, 0);
+    g.load_data();
     int kc_c = min(KT, d1.kext), kpos_c = 0, kext_c = d1.kext;
     auto advance = [&]() {
       k1 += KT;
@@ -304,13 +235,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
         ++p1;
         k1 = 0;
         if (p1 < pe) {
-          d1 = pairs[p1];
-          g.setup_pair(d1, pool, w.m0, w.n0, blk.mext, blk.next);
+          d1 = wave_uniform(sload(pairs + p1));
+          g.setup_pair(d1, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next);
         } else {
           ok = false;
         }
       }
-      if (ok) g.load_kofs(d1, pool, k1);
+      if (ok) g.load_tables(d1, pool, k1);
       return ok;
     };
     bool has1 = advance();
@@ -324,7 +255,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
       const int kc_now = kc_c, kpos_now = kpos_c, kext_now = kext_c;
       bool has2 = false;
       if (has1) {
-        g.load_data(pr.A, pr.B);
+        g.load_data();
         kc_c = min(KT, d1.kext - k1);
         kpos_c = k1;
         kext_c = d1.kext;
@@ -383,14 +314,14 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
   const int wm = wave % WGM, wn = wave / WGM, lr = lane & 15, lq = lane >> 4;
   const int item = blockIdx.x;
   if (item >= P.n_work) return;
-  const WorkItem w = P.work[item];
-  const ProblemDesc& pr = P.probs ? P.probs[w.prob] : P.single;
-  const OutBlockDesc blk = pr.blocks[w.ob];
+  const WorkItem w = wave_uniform(sload(P.work + item));
+  const ProblemDesc pr = wave_uniform(P.probs ? sload(P.probs + w.prob) : P.single);
+  const OutBlockDesc blk = wave_uniform(sload(pr.blocks + w.ob));
   const int32_t* __restrict__ pool = pr.pool;
   const PairDesc* __restrict__ pairs = pr.pairs + blk.pair_base;
   const uint64_t* Ap = reinterpret_cast<const uint64_t*>(pr.A);
   const uint64_t* Bp = reinterpret_cast<const uint64_t*>(pr.B);
-  const int cnt = pr.counts[w.ob];
+  const int cnt = wave_uniform(gload(pr.counts + w.ob));
   int pb = 0, pe = cnt;
   if (pr.k_splits > 1) {
     pb = (int)(((int64_t)cnt * w.split) / pr.k_splits);
@@ -409,11 +340,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
       rest[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
     }
   if (pb < pe) {
-    PairDesc d1 = pairs[pb];
+    PairDesc d1 = wave_uniform(sload(pairs + pb));
     int p1 = pb, k1 = 0;
-    g.setup_pair(d1, pool, w.m0, w.n0, blk.mext, blk.next);
-    g.load_kofs(d1, pool, 0);
-    g.load_data(Ap, Bp);
+    g.setup_pair(d1, pool, Ap, Bp, w.m0, w.n0, blk.mext, blk.next);
+    g.load_tables(d1, pool, 0);
+    g.load_data();
     int kc_c = min(KT, d1.kext), kpos_c = 0, kext_c = d1.kext;
     auto advance = [&]() {
       k1 += KT;
@@ -422,13 +353,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
         ++p1;
         k1 = 0;
         if (p1 < pe) {
-          d1 = pairs[p1];
-          g.setup_pair(d1, pool, w.m0, w.n0, blk.mext, blk.next);
+          d1 = wave_uniform(sload(pairs + p1));
+          g.setup_pair(d1, pool, Ap, Bp, w.m0, w.n0, blk.mext, blk.next);
         } else {
           ok = false;
         }
       }
-      if (ok) g.load_kofs(d1, pool, k1);
+      if (ok) g.load_tables(d1, pool, k1);
       return ok;
     };
     bool has1 = advance();
@@ -450,7 +381,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
       const int kc_now = kc_c, kpos_now = kpos_c, kext_now = kext_c;
       bool has2 = false;
       if (has1) {
-        g.load_data(Ap, Bp);
+        g.load_data();
         kc_c = min(KT, d1.kext - k1);
         kpos_c = k1;
         kext_c = d1.kext;
