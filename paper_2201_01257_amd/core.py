@@ -7,12 +7,28 @@ epilogue) runs in the HIP library.  PyTorch supplies device memory and the curre
 from __future__ import annotations
 
 import ctypes
+import sys
 from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
 from . import _lib
 from ._lib import NONZERO_FN, PlanStats, TammError, check, load
+
+
+def _destroy(obj, fname: str, _lib_mod=_lib, _sys=sys) -> None:
+    """Release a library handle from ``__del__``; a no-op while the interpreter shuts down, when
+    module globals and the HIP runtime may already be gone."""
+    h = getattr(obj, "_h", None)
+    if not h:
+        return
+    obj._h = None
+    try:
+        if _sys.is_finalizing() or _lib_mod._lib is None:
+            return
+        getattr(_lib_mod._lib, fname)(h)
+    except Exception:  # noqa: BLE001 - destructors must not raise
+        pass
 
 PRECISIONS = {"f64": 0, "f32": 1, "bf16x3": 2, "bf16x4_aligned": 3}
 
@@ -75,10 +91,8 @@ class Space:
                                        len(s), ctypes.byref(h)))
         return cls(h.value)
 
-    def __del__(self):
-        if getattr(self, "_h", None) and _lib._lib is not None:
-            _lib._lib.tamm_space_destroy(self._h)
-            self._h = None
+    def __del__(self, _d=_destroy):
+        _d(self, "tamm_space_destroy")
 
 
 class Tensor:
@@ -213,11 +227,9 @@ class Tensor:
             d[tuple(slice(l, l + e) for l, e in zip(lo, ext))] = flat[off:off + int(np.prod(ext))].reshape(ext)
         return d
 
-    def __del__(self):
-        if getattr(self, "_h", None) and _lib._lib is not None:
-            self._plans = {}
-            _lib._lib.tamm_tensor_destroy(self._h)
-            self._h = None
+    def __del__(self, _d=_destroy):
+        self._plans = {}
+        _d(self, "tamm_tensor_destroy")
 
 
 class Plan:
@@ -304,10 +316,8 @@ class Plan:
             res.append(lst)
         return res
 
-    def __del__(self):
-        if getattr(self, "_h", None) and _lib._lib is not None:
-            _lib._lib.tamm_plan_destroy(self._h)
-            self._h = None
+    def __del__(self, _d=_destroy):
+        _d(self, "tamm_plan_destroy")
 
 
 def contract(out: Tensor, ol: str, lhs: Tensor, ll: str, rhs: Tensor, rl: str, alpha: float = 1.0,
@@ -347,10 +357,8 @@ class Denominator:
         s = current_stream_handle() if stream is None else stream
         check(load().tamm_denominator_execute(self._h, self._eptr, s))
 
-    def __del__(self):
-        if getattr(self, "_h", None) and _lib._lib is not None:
-            _lib._lib.tamm_denominator_destroy(self._h)
-            self._h = None
+    def __del__(self, _d=_destroy):
+        _d(self, "tamm_denominator_destroy")
 
 
 class Group:
@@ -419,10 +427,8 @@ class Group:
         self.bind_workspace(best)
         check(lib.tamm_group_autotune(self._h, s, cache_path.encode(), reps))
 
-    def __del__(self):
-        if getattr(self, "_h", None) and _lib._lib is not None:
-            _lib._lib.tamm_group_destroy(self._h)
-            self._h = None
+    def __del__(self, _d=_destroy):
+        _d(self, "tamm_group_destroy")
 
 
 __all__ = ["Space", "Tensor", "Plan", "Group", "contract", "Denominator", "TammError", "PRECISIONS"]

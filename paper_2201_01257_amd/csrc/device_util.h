@@ -118,30 +118,39 @@ namespace tamm {
 // Per-thread gather state of one contraction workgroup (shared by the float64 and mixed kernels).
 //
 // A chunk of A is MT rows x KT summed indices, of B NT rows x KT.  With a k-contiguous operand
-// (its stride-1 label is summed) the lanes run along k: a thread owns one k and AE (BE) rows;
-// otherwise the lanes run along the rows: a thread owns one row and AE (BE) k positions.
-// Element e of a thread lands in LDS at row X_r0 + e*X_DR, k X_k0 + e*X_DK.
+// (its stride-1 label is summed) the lanes run along k: a thread owns one k and AE (BE) rows.
+// Otherwise the lanes run along the rows: element e of a thread is the flat position
+// tid + e*NTHR of the [k][row] chunk, so consecutive lanes read consecutive rows.  When the row
+// count divides the thread count a thread keeps one row and AE (BE) k positions; otherwise
+// (e.g. 80 rows, 256 threads) every element has its own row and k.
 //
 // Everything is branch-free: table entries are fetched at clamped (always valid) positions and
 // their validity is kept aside; the data load of an invalid element uses kOutOfRange as its byte
-// offset and the buffer hardware returns zero.  Table entries of the chunk after next are
-// fetched while the data of the next chunk is in flight, so no dependent table->data chain
-// sits in front of the MFMAs.
+// offset and the buffer hardware returns zero.  Table entries are fetched a chunk ahead of the
+// data, so no dependent table->data chain sits in front of the MFMAs.
+template <int R, int KT, int NTHR, bool KC>
+struct GatherMap {
+  static constexpr int E = R * KT / NTHR;                       // elements per thread
+  static constexpr bool ROW_FIXED = !KC && (NTHR % R == 0);     // one row per thread
+  static constexpr int NR = KC ? E : (ROW_FIXED ? 1 : E);       // distinct row-table entries
+  static constexpr int NK = KC ? 1 : E;                         // distinct k-table entries
+  static_assert(R * KT % NTHR == 0, "chunk elements must split evenly over the threads");
+  static_assert(!KC || (NTHR % KT == 0 && R % (NTHR / KT) == 0), "k-contiguous gather mapping");
+  static_assert(E <= 32, "validity masks hold 32 elements");
+  __device__ static int row(int tid, int e) { return KC ? tid / KT + e * (NTHR / KT) : (tid + e * NTHR) % R; }
+  __device__ static int k(int tid, int e) { return KC ? tid % KT : (tid + e * NTHR) / R; }
+  __device__ static int ridx(int e) { return KC ? e : (ROW_FIXED ? 0 : e); }  // row entry of element e
+  __device__ static int kidx(int e) { return KC ? 0 : e; }                    // k entry of element e
+};
+
 template <int MT, int NT, int KT, int NTHR, bool A_KC, bool B_KC, typename T>
 struct Gather {
-  static constexpr int AE = MT * KT / NTHR;
-  static constexpr int BE = NT * KT / NTHR;
-  static constexpr int A_NR = A_KC ? AE : 1, A_NK = A_KC ? 1 : AE;
-  static constexpr int B_NR = B_KC ? BE : 1, B_NK = B_KC ? 1 : BE;
-  static constexpr int A_DR = A_KC ? NTHR / KT : 0, A_DK = A_KC ? 0 : NTHR / MT;
-  static constexpr int B_DR = B_KC ? NTHR / KT : 0, B_DK = B_KC ? 0 : NTHR / NT;
-  static_assert(!A_KC || (NTHR % KT == 0 && MT % (NTHR / KT) == 0), "k-contiguous A gather mapping");
-  static_assert(!B_KC || (NTHR % KT == 0 && NT % (NTHR / KT) == 0), "k-contiguous B gather mapping");
-  static_assert(A_KC || (NTHR % MT == 0 && KT % (NTHR / MT) == 0), "m-contiguous A gather mapping");
-  static_assert(B_KC || (NTHR % NT == 0 && KT % (NTHR / NT) == 0), "n-contiguous B gather mapping");
-  static_assert(AE <= 32 && BE <= 32, "validity masks hold 32 elements");
+  using MA = GatherMap<MT, KT, NTHR, A_KC>;
+  using MB = GatherMap<NT, KT, NTHR, B_KC>;
+  static constexpr int AE = MA::E, BE = MB::E;
+  static constexpr int A_NR = MA::NR, A_NK = MA::NK, B_NR = MB::NR, B_NK = MB::NK;
 
-  int a_k0, a_r0, b_k0, b_r0;
+  int tid;
   const T* a_base;                        // current pair's operand blocks
   const T* b_base;
   uint32_t a_bytes, b_bytes;
@@ -150,12 +159,7 @@ struct Gather {
   uint32_t a_rok, b_rok, a_kok, b_kok;    // validity bits
   T ra[AE], rb[BE];
 
-  __device__ void init(int tid) {
-    a_k0 = A_KC ? tid % KT : tid / MT;
-    a_r0 = A_KC ? tid / KT : tid % MT;
-    b_k0 = B_KC ? tid % KT : tid / NT;
-    b_r0 = B_KC ? tid / KT : tid % NT;
-  }
+  __device__ void init(int t) { tid = t; }
   __device__ void setup_pair(const PairDesc& d, const int32_t* pool, const T* A, const T* B, int m0, int n0, int mext,
                              int next) {
     a_base = A + d.a_off;
@@ -166,13 +170,13 @@ struct Gather {
     b_rok = 0;
 #pragma unroll
     for (int e = 0; e < A_NR; ++e) {
-      const int m = m0 + a_r0 + e * A_DR;
+      const int m = m0 + MA::row(tid, e);
       a_rt[e] = gload(pool + d.a_tabM + min(m, mext - 1));
       a_rok |= (m < mext ? 1u : 0u) << e;
     }
 #pragma unroll
     for (int e = 0; e < B_NR; ++e) {
-      const int n = n0 + b_r0 + e * B_DR;
+      const int n = n0 + MB::row(tid, e);
       b_rt[e] = gload(pool + d.b_tabN + min(n, next - 1));
       b_rok |= (n < next ? 1u : 0u) << e;
     }
@@ -182,13 +186,13 @@ struct Gather {
     b_kok = 0;
 #pragma unroll
     for (int e = 0; e < A_NK; ++e) {
-      const int k = kbase + a_k0 + e * A_DK;
+      const int k = kbase + MA::k(tid, e);
       a_kt[e] = gload(pool + d.a_tabK + min(k, d.kext - 1));
       a_kok |= (k < d.kext ? 1u : 0u) << e;
     }
 #pragma unroll
     for (int e = 0; e < B_NK; ++e) {
-      const int k = kbase + b_k0 + e * B_DK;
+      const int k = kbase + MB::k(tid, e);
       b_kt[e] = gload(pool + d.b_tabK + min(k, d.kext - 1));
       b_kok |= (k < d.kext ? 1u : 0u) << e;
     }
@@ -199,23 +203,95 @@ struct Gather {
     const __amdgpu_buffer_rsrc_t b_rsrc = block_rsrc(b_base, b_bytes);
 #pragma unroll
     for (int e = 0; e < AE; ++e) {
-      const int er = A_KC ? e : 0, ek = A_KC ? 0 : e;
+      const int er = MA::ridx(e), ek = MA::kidx(e);
       const bool ok = ((a_rok >> er) & (a_kok >> ek) & 1u) != 0;
       const uint32_t off = ok ? (uint32_t)(a_rt[er] + a_kt[ek]) * 8u : kOutOfRange;
       ra[e] = buffer_load8<T>(a_rsrc, off);
     }
 #pragma unroll
     for (int e = 0; e < BE; ++e) {
-      const int er = B_KC ? e : 0, ek = B_KC ? 0 : e;
+      const int er = MB::ridx(e), ek = MB::kidx(e);
       const bool ok = ((b_rok >> er) & (b_kok >> ek) & 1u) != 0;
       const uint32_t off = ok ? (uint32_t)(b_rt[er] + b_kt[ek]) * 8u : kOutOfRange;
       rb[e] = buffer_load8<T>(b_rsrc, off);
     }
   }
-  __device__ int a_lds_row(int e) const { return a_r0 + e * A_DR; }
-  __device__ int a_lds_k(int e) const { return a_k0 + e * A_DK; }
-  __device__ int b_lds_row(int e) const { return b_r0 + e * B_DR; }
-  __device__ int b_lds_k(int e) const { return b_k0 + e * B_DK; }
+  __device__ int a_lds_row(int e) const { return MA::row(tid, e); }
+  __device__ int a_lds_k(int e) const { return MA::k(tid, e); }
+  __device__ int b_lds_row(int e) const { return MB::row(tid, e); }
+  __device__ int b_lds_k(int e) const { return MB::k(tid, e); }
 };
+
+
+// Chunk pipeline of one work item, shared by the contraction kernels.  LDS holds two chunk
+// buffers and there is one barrier per chunk: while compute(buf, ...) runs the MFMAs of chunk c
+// from buffer `buf`, the hook it calls after its first k-step stores chunk c+1 (in registers
+// since the previous chunk) into the other buffer, issues the global loads of chunk c+2 into the
+// same registers and fetches the table entries of chunk c+3.  `flush` tells compute that chunk c
+// ends a promotion window of W summed indices or a pair (W = 0: pairs only); the flags travel
+// with the chunks in a small FIFO.  Chunks run over pairs [pb, pe) and KT-long pieces of each.
+template <int KT, int W, typename G, typename T, typename StoreF, typename ComputeF>
+__device__ __forceinline__ void chunk_pipeline(G& g, const PairDesc* pairs, int pb, int pe, const int32_t* pool,
+                                               const T* A, const T* B, int m0, int n0, int mext, int next,
+                                               StoreF&& store, ComputeF&& compute) {
+  PairDesc d1 = wave_uniform(sload(pairs + pb));  // pair of the chunk whose tables were fetched last
+  int p1 = pb, k1 = 0;
+  uint32_t fifo = 0;  // flush flags of fetched chunks not yet computed, oldest in bit 0
+  int nf = 0;
+  auto push = [&]() {
+    const int kend = k1 + KT;
+    const bool f = kend >= d1.kext || (W > 0 && kend % W == 0);
+    fifo |= (f ? 1u : 0u) << nf;
+    ++nf;
+  };
+  auto advance = [&]() {  // table entries of the next chunk; false past the last one
+    k1 += KT;
+    if (k1 >= d1.kext) {
+      ++p1;
+      k1 = 0;
+      if (p1 >= pe) return false;
+      d1 = wave_uniform(sload(pairs + p1));
+      g.setup_pair(d1, pool, A, B, m0, n0, mext, next);
+    }
+    g.load_tables(d1, pool, k1);
+    push();
+    return true;
+  };
+  // prologue: chunk 0 into buffer 0, chunk 1 in flight, table entries of chunk 2 in flight
+  g.setup_pair(d1, pool, A, B, m0, n0, mext, next);
+  g.load_tables(d1, pool, 0);
+  push();
+  g.load_data();
+  bool inflight = advance();  // the next chunk's data is in registers (or on its way)
+  store(0);
+  bool tabs = false;          // the table entries of the chunk after it are
+  if (inflight) {
+    g.load_data();
+    tabs = advance();
+  }
+  __syncthreads();
+  int buf = 0;
+  while (true) {
+    const bool flush = (fifo & 1u) != 0;
+    fifo >>= 1;
+    --nf;
+    bool inflight_next = false, tabs_next = false;
+    compute(buf, flush, [&]() {
+      if (inflight) {
+        store(buf ^ 1);
+        if (tabs) {
+          g.load_data();
+          inflight_next = true;
+          tabs_next = advance();
+        }
+      }
+    });
+    __syncthreads();  // buffer `buf` is free again; the other one holds the next chunk
+    if (!inflight) break;
+    inflight = inflight_next;
+    tabs = tabs_next;
+    buf ^= 1;
+  }
+}
 
 }  // namespace tamm

@@ -78,12 +78,17 @@ hipError_t launch_screen(const ScreenParams& p, hipStream_t s) {
 // gathered from the operand blocks through the plan's offset tables straight into LDS; the
 // thread-to-element mapping follows the operand's stride-1 label (lanes along k when it is a
 // summed label, along m/n otherwise) so that global reads coalesce.  Both operands sit in LDS as
-// [row][k] with a row stride of KT+2 doubles, which keeps the MFMA operand reads free of bank
-// conflicts.  There is no separate permutation pass.
+// [row][k] with an odd row stride of KT+1 doubles, so that 16 consecutive rows (or k positions)
+// touch 16 distinct bank pairs: the gather stores and the MFMA operand reads are conflict-free.
+// There is no separate permutation pass.
 //
-// Software pipeline (three chunks in flight): while the MFMAs of chunk c run from LDS, the data
-// of chunk c+1 is in flight into registers and the offset-table entries of chunk c+2 are in
-// flight too, so no dependent table->data load chain sits in front of the MFMAs.
+// Software pipeline with one barrier per chunk: LDS holds two chunk buffers.  While the MFMAs
+// of chunk c run from one buffer, the registers holding chunk c+1 (loaded during the previous
+// chunk's MFMAs) are stored into the other buffer, the global loads of chunk c+2 are issued into
+// the same registers, and the offset-table entries of chunk c+3 are fetched.  Inside a chunk the
+// MFMA operands of k-step s+1 are read from LDS while the MFMAs of step s run.  Every MFMA
+// block of the tile runs (padding rows, columns and k positions hold zeros), so the MFMA stream
+// has no branches.
 //
 // v_mfma_f64_16x16x4_f64 lane layout (gfx950, checked on the device): A[m][k] comes from lane
 // m + 16k, B[k][n] from lane n + 16k, and D[m][n] lands in lane n + 16*(m%4), register m/4.
@@ -93,25 +98,28 @@ hipError_t launch_screen(const ScreenParams& p, hipStream_t s) {
 // workspace and k_reduce sums them in split order.  Results are bitwise reproducible.
 //
 // Launch modes: one workgroup per work item, or a persistent grid whose workgroups take items
-// from a counter (the grouped launch); the item order is the plan's longest-first order.  The
-// operands' gather layouts (A_KC, B_KC) are template parameters: "layout" = 2*A_KC + B_KC.
+// from a counter (the grouped launch); the item order is the plan's.  The operands' gather
+// layouts (A_KC, B_KC) are template parameters: "layout" = 2*A_KC + B_KC.
 // ---------------------------------------------------------------------------------------------
 template <int MT, int NT, int KT, int WGM, int WGN, bool A_KC, bool B_KC>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f64(ContractParams P) {
   constexpr int NTHR = 64 * WGM * WGN;
   constexpr int WM = MT / WGM, WN = NT / WGN;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int LD = KT + 2;  // LDS row stride in doubles
+  constexpr int LD = KT + 1;  // LDS row stride in doubles (odd: conflict-free)
+  constexpr int NS = KT / 4;  // MFMA k-steps per chunk
   static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile must be a multiple of 16");
-  static_assert(KT % 4 == 0, "KT multiple of 4");
+  static_assert(KT % 4 == 0 && NS >= 2, "KT a multiple of 4, at least 8");
   using G = Gather<MT, NT, KT, NTHR, A_KC, B_KC, double>;
-  __shared__ double As[MT * LD];
-  __shared__ double Bs[NT * LD];
+  __shared__ double As[2][MT * LD];
+  __shared__ double Bs[2][NT * LD];
   __shared__ int s_next;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
   const int lr = lane & 15, lq = lane >> 4;
+  const int a_frag = (wm * WM + lr) * LD + lq;  // this lane's operand reads at k-step 0
+  const int b_frag = (wn * WN + lr) * LD + lq;
   G g;
   g.init(tid);
 
@@ -129,10 +137,6 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f64(ContractParams 
       pb = (int)(((int64_t)cnt * w.split) / pr.k_splits);
       pe = (int)(((int64_t)cnt * (w.split + 1)) / pr.k_splits);
     }
-    // MFMA blocks of this wave that hold at least one valid row / column (uniform per wave)
-    const int fm_valid = wave_uniform(min(FM, max(0, (blk.mext - w.m0 - wm * WM + 15) >> 4)));
-    const int fn_valid = wave_uniform(min(FN, max(0, (blk.next - w.n0 - wn * WN + 15) >> 4)));
-    const bool full = fm_valid == FM && fn_valid == FN;
 
     d4_t acc[FM][FN];
 #pragma unroll
@@ -141,65 +145,38 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f64(ContractParams 
       for (int j = 0; j < FN; ++j) acc[i][j] = (d4_t){0.0, 0.0, 0.0, 0.0};
 
     if (pb < pe) {
-      // chunk cursors: c = next into LDS, n1 = data in flight, n2 = table entries in flight
-      PairDesc d1 = wave_uniform(sload(pairs + pb));
-      int p1 = pb, k1 = 0;
-      g.setup_pair(d1, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next);
-      g.load_tables(d1, pool, 0);
-      g.load_data();
-      auto advance = [&]() {
-        k1 += KT;
-        if (k1 >= d1.kext) {
-          ++p1;
-          k1 = 0;
-          if (p1 >= pe) return false;
-          d1 = wave_uniform(sload(pairs + p1));
-          g.setup_pair(d1, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next);
-        }
-        g.load_tables(d1, pool, k1);
-        return true;
+      auto store = [&](int b) {
+#pragma unroll
+        for (int e = 0; e < G::AE; ++e) As[b][g.a_lds_row(e) * LD + g.a_lds_k(e)] = g.ra[e];
+#pragma unroll
+        for (int e = 0; e < G::BE; ++e) Bs[b][g.b_lds_row(e) * LD + g.b_lds_k(e)] = g.rb[e];
       };
-      bool has1 = advance();
-      while (true) {
-        __syncthreads();  // the previous chunk's LDS reads are complete
+      auto compute = [&](int b, bool, auto&& hook) {
+        const double* as = As[b] + a_frag;
+        const double* bs = Bs[b] + b_frag;
+        double af[2][FM], bf[2][FN];
 #pragma unroll
-        for (int e = 0; e < G::AE; ++e) As[g.a_lds_row(e) * LD + g.a_lds_k(e)] = g.ra[e];
+        for (int i = 0; i < FM; ++i) af[0][i] = as[i * 16 * LD];
 #pragma unroll
-        for (int e = 0; e < G::BE; ++e) Bs[g.b_lds_row(e) * LD + g.b_lds_k(e)] = g.rb[e];
-        __syncthreads();
-        bool has2 = false;
-        if (has1) {
-          g.load_data();  // chunk n1 (its table entries arrived during the previous MFMA phase)
-          has2 = advance();
-        }
-        // All KT/4 k-steps run, unrolled so that the LDS reads of step s+1 overlap the MFMAs of
-        // step s; a ragged last chunk of a pair holds zeros beyond its K extent.  MFMA blocks
-        // wholly outside the output block are skipped.
+        for (int j = 0; j < FN; ++j) bf[0][j] = bs[j * 16 * LD];
 #pragma unroll
-        for (int s = 0; s < KT / 4; ++s) {
-          const int k = 4 * s + lq;
-          double af[FM], bf[FN];
+        for (int s = 0; s < NS; ++s) {
+          const int cur = s & 1, nxt = cur ^ 1;
+          if (s + 1 < NS) {  // operands of the next k-step while this step's MFMAs run
 #pragma unroll
-          for (int i = 0; i < FM; ++i) af[i] = As[(wm * WM + i * 16 + lr) * LD + k];
+            for (int i = 0; i < FM; ++i) af[nxt][i] = as[i * 16 * LD + 4 * (s + 1)];
 #pragma unroll
-          for (int j = 0; j < FN; ++j) bf[j] = Bs[(wn * WN + j * 16 + lr) * LD + k];
-          if (full) {
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
-#pragma unroll
-              for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-          } else {
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
-#pragma unroll
-              for (int j = 0; j < FN; ++j)
-                if (i < fm_valid && j < fn_valid)
-                  acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < FN; ++j) bf[nxt][j] = bs[j * 16 * LD + 4 * (s + 1)];
           }
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[cur][i], bf[cur][j], acc[i][j], 0, 0, 0);
+          if (s == 0) hook();
         }
-        if (!has1) break;
-        has1 = has2;
-      }
+      };
+      chunk_pipeline<KT, 0>(g, pairs, pb, pe, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next, store, compute);
     }
 
     // epilogue: lane holds D[m][n] for m = 4r + lane/16 (register r), n = lane%16
@@ -224,19 +201,19 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f64(ContractParams 
         for (int r = 0; r < 4; ++r) {
           const int m = w.m0 + wm * WM + i * 16 + 4 * r + lq;
           if (m >= blk.mext) continue;
-          const int64_t rowoff = blk.c_off + pool[blk.c_tabM + m];
+          const int64_t rowoff = blk.c_off + gload(pool + blk.c_tabM + m);
 #pragma unroll
           for (int j = 0; j < FN; ++j) {
             const int n = w.n0 + wn * WN + j * 16 + lr;
             if (n >= blk.next) continue;
-            const int64_t idx = rowoff + pool[blk.c_tabN + n];
+            const int64_t idx = rowoff + gload(pool + blk.c_tabN + n);
             const double v = alpha * acc[i][j][r];
             Cg[idx] = (beta == 0.0) ? v : beta * Cg[idx] + v;
           }
         }
     }
     if (!P.next_item) break;
-    __syncthreads();  // LDS and s_next are free
+    __syncthreads();  // s_next is free
     if (tid == 0) s_next = atomicAdd(P.next_item, 1);
     __syncthreads();
     item = s_next;
@@ -287,11 +264,12 @@ static const F64Config kF64Configs[] = {
     {64, 128, 16, 2, 2, "f64_m64n128k16_w2x2"},
     {128, 128, 16, 2, 2, "f64_m128n128k16_w2x2"},
     {32, 64, 16, 2, 2, "f64_m32n64k16_w2x2"},
-    {128, 128, 32, 2, 2, "f64_m128n128k32_w2x2"},
-    {128, 64, 32, 2, 2, "f64_m128n64k32_w2x2"},
-    {64, 128, 32, 2, 2, "f64_m64n128k32_w2x2"},
+    {128, 80, 16, 4, 1, "f64_m128n80k16_w4x1"},
+    {80, 128, 16, 1, 4, "f64_m80n128k16_w1x4"},
+    {64, 80, 16, 4, 1, "f64_m64n80k16_w4x1"},
     {32, 256, 16, 1, 4, "f64_m32n256k16_w1x4"},
     {256, 32, 16, 4, 1, "f64_m256n32k16_w4x1"},
+    {128, 128, 32, 2, 2, "f64_m128n128k32_w2x2"},
 };
 
 int f64_config_count() { return (int)(sizeof(kF64Configs) / sizeof(kF64Configs[0])); }
@@ -317,11 +295,12 @@ hipError_t launch_contract_f64(int config, int layout, const ContractParams& p, 
     case 2: return launch_cfg<64, 128, 16, 2, 2>(layout, p, grid, s);
     case 3: return launch_cfg<128, 128, 16, 2, 2>(layout, p, grid, s);
     case 4: return launch_cfg<32, 64, 16, 2, 2>(layout, p, grid, s);
-    case 5: return launch_cfg<128, 128, 32, 2, 2>(layout, p, grid, s);
-    case 6: return launch_cfg<128, 64, 32, 2, 2>(layout, p, grid, s);
-    case 7: return launch_cfg<64, 128, 32, 2, 2>(layout, p, grid, s);
+    case 5: return launch_cfg<128, 80, 16, 4, 1>(layout, p, grid, s);
+    case 6: return launch_cfg<80, 128, 16, 1, 4>(layout, p, grid, s);
+    case 7: return launch_cfg<64, 80, 16, 4, 1>(layout, p, grid, s);
     case 8: return launch_cfg<32, 256, 16, 1, 4>(layout, p, grid, s);
     case 9: return launch_cfg<256, 32, 16, 4, 1>(layout, p, grid, s);
+    case 10: return launch_cfg<128, 128, 32, 2, 2>(layout, p, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

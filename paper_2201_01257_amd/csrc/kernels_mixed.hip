@@ -193,10 +193,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
   constexpr int LD = KT + 4;  // floats; rows 16 apart land on distinct banks for the 4 k lanes
   static_assert(kSplitWindow % KT == 0, "chunks tile the promotion window");
   using G = Gather<MT, NT, KT, NTHR, A_KC, B_KC, double>;
-  __shared__ float As[MT * LD];
-  __shared__ float Bs[NT * LD];
+  __shared__ float As[2][MT * LD];
+  __shared__ float Bs[2][NT * LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM, lr = lane & 15, lq = lane >> 4;
+  const int a_frag = (wm * WM + lr) * LD + lq, b_frag = (wn * WN + lr) * LD + lq;
   const int item = blockIdx.x;
   if (item >= P.n_work) return;
   const WorkItem w = wave_uniform(sload(P.work + item));
@@ -222,59 +223,37 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
       part[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
     }
   if (pb < pe) {
-    PairDesc d1 = wave_uniform(sload(pairs + pb));
-    int p1 = pb, k1 = 0;
-    g.setup_pair(d1, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next);
-    g.load_tables(d1, pool, 0);
-    g.load_data();
-    int kc_c = min(KT, d1.kext), kpos_c = 0, kext_c = d1.kext;
-    auto advance = [&]() {
-      k1 += KT;
-      bool ok = true;
-      if (k1 >= d1.kext) {
-        ++p1;
-        k1 = 0;
-        if (p1 < pe) {
-          d1 = wave_uniform(sload(pairs + p1));
-          g.setup_pair(d1, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next);
-        } else {
-          ok = false;
-        }
-      }
-      if (ok) g.load_tables(d1, pool, k1);
-      return ok;
+    auto store = [&](int b) {
+#pragma unroll
+      for (int e = 0; e < G::AE; ++e) As[b][g.a_lds_row(e) * LD + g.a_lds_k(e)] = (float)g.ra[e];
+#pragma unroll
+      for (int e = 0; e < G::BE; ++e) Bs[b][g.b_lds_row(e) * LD + g.b_lds_k(e)] = (float)g.rb[e];
     };
-    bool has1 = advance();
-    while (true) {
-      __syncthreads();
+    auto compute = [&](int b, bool flush, auto&& hook) {
+      const float* as = As[b] + a_frag;
+      const float* bs = Bs[b] + b_frag;
+      float af[2][FM], bf[2][FN];
 #pragma unroll
-      for (int e = 0; e < G::AE; ++e) As[g.a_lds_row(e) * LD + g.a_lds_k(e)] = (float)g.ra[e];
+      for (int i = 0; i < FM; ++i) af[0][i] = as[i * 16 * LD];
 #pragma unroll
-      for (int e = 0; e < G::BE; ++e) Bs[g.b_lds_row(e) * LD + g.b_lds_k(e)] = (float)g.rb[e];
-      __syncthreads();
-      const int kc_now = kc_c, kpos_now = kpos_c, kext_now = kext_c;
-      bool has2 = false;
-      if (has1) {
-        g.load_data();
-        kc_c = min(KT, d1.kext - k1);
-        kpos_c = k1;
-        kext_c = d1.kext;
-        has2 = advance();
-      }
+      for (int j = 0; j < FN; ++j) bf[0][j] = bs[j * 16 * LD];
 #pragma unroll
       for (int s = 0; s < KT / 4; ++s) {  // zeros beyond a ragged chunk's K extent
-        float af[FM], bf[FN];
+        const int cur = s & 1, nxt = cur ^ 1;
+        if (s + 1 < KT / 4) {
 #pragma unroll
-        for (int i = 0; i < FM; ++i) af[i] = As[(wm * WM + i * 16 + lr) * LD + 4 * s + lq];
+          for (int i = 0; i < FM; ++i) af[nxt][i] = as[i * 16 * LD + 4 * (s + 1)];
 #pragma unroll
-        for (int j = 0; j < FN; ++j) bf[j] = Bs[(wn * WN + j * 16 + lr) * LD + 4 * s + lq];
+          for (int j = 0; j < FN; ++j) bf[nxt][j] = bs[j * 16 * LD + 4 * (s + 1)];
+        }
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-          for (int j = 0; j < FN; ++j) part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], part[i][j], 0, 0, 0);
+          for (int j = 0; j < FN; ++j)
+            part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[cur][i], bf[cur][j], part[i][j], 0, 0, 0);
+        if (s == 0) hook();
       }
-      const int kend = kpos_now + kc_now;
-      if (kend % kSplitWindow == 0 || kend >= kext_now) {
+      if (flush) {  // end of a promotion window or of a pair: float32 sums into float64
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -285,9 +264,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
               part[i][j][r] = 0.f;
             }
       }
-      if (!has1) break;
-      has1 = has2;
-    }
+    };
+    chunk_pipeline<KT, kSplitWindow>(g, pairs, pb, pe, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next, store, compute);
   }
   epilogue_f32layout<MT, NT, WM, WN, FM, FN>(pr, w, blk, acc, wm, wn, lr, lq);
 }
@@ -306,12 +284,11 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
   static_assert(KT % 32 == 0 && kSplitWindow % KT == 0, "chunks of whole MFMA k-steps tile the window");
   static_assert(((LD * 2) / 16) % 2 == 1, "row stride must be an odd number of 16-byte units");
   using G = Gather<MT, NT, KT, NTHR, A_KC, B_KC, uint64_t>;
-  __shared__ __attribute__((aligned(16))) __bf16 As[NS * MT * LD];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[NS * NT * LD];
-  unsigned short* As16 = reinterpret_cast<unsigned short*>(As);
-  unsigned short* Bs16 = reinterpret_cast<unsigned short*>(Bs);
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][NS * MT * LD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][NS * NT * LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM, lr = lane & 15, lq = lane >> 4;
+  const int a_frag = (wm * WM + lr) * LD + 8 * lq, b_frag = (wn * WN + lr) * LD + 8 * lq;
   const int item = blockIdx.x;
   if (item >= P.n_work) return;
   const WorkItem w = wave_uniform(sload(P.work + item));
@@ -340,31 +317,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
       rest[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
     }
   if (pb < pe) {
-    PairDesc d1 = wave_uniform(sload(pairs + pb));
-    int p1 = pb, k1 = 0;
-    g.setup_pair(d1, pool, Ap, Bp, w.m0, w.n0, blk.mext, blk.next);
-    g.load_tables(d1, pool, 0);
-    g.load_data();
-    int kc_c = min(KT, d1.kext), kpos_c = 0, kext_c = d1.kext;
-    auto advance = [&]() {
-      k1 += KT;
-      bool ok = true;
-      if (k1 >= d1.kext) {
-        ++p1;
-        k1 = 0;
-        if (p1 < pe) {
-          d1 = wave_uniform(sload(pairs + p1));
-          g.setup_pair(d1, pool, Ap, Bp, w.m0, w.n0, blk.mext, blk.next);
-        } else {
-          ok = false;
-        }
-      }
-      if (ok) g.load_tables(d1, pool, k1);
-      return ok;
-    };
-    bool has1 = advance();
-    while (true) {
-      __syncthreads();
+    auto store = [&](int b) {
+      unsigned short* As16 = reinterpret_cast<unsigned short*>(As[b]);
+      unsigned short* Bs16 = reinterpret_cast<unsigned short*>(Bs[b]);
 #pragma unroll
       for (int e = 0; e < G::AE; ++e) {
         const int o = g.a_lds_row(e) * LD + g.a_lds_k(e);
@@ -377,16 +332,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
 #pragma unroll
         for (int s = 0; s < NS; ++s) Bs16[s * NT * LD + o] = (unsigned short)(g.rb[e] >> (16 * s));
       }
-      __syncthreads();
-      const int kc_now = kc_c, kpos_now = kpos_c, kext_now = kext_c;
-      bool has2 = false;
-      if (has1) {
-        g.load_data();
-        kc_c = min(KT, d1.kext - k1);
-        kpos_c = k1;
-        kext_c = d1.kext;
-        has2 = advance();
-      }
+    };
+    auto compute = [&](int b, bool flush, auto&& hook) {
 #pragma unroll
       for (int st = 0; st < KT / 32; ++st) {  // zeros beyond a ragged chunk's K extent
         bf8_t af[NS][FM], bfr[NS][FN];
@@ -394,18 +341,19 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
         for (int s = 0; s < NS; ++s) {
 #pragma unroll
           for (int i = 0; i < FM; ++i)
-            af[s][i] = *reinterpret_cast<const bf8_t*>(&As[s * MT * LD + (wm * WM + i * 16 + lr) * LD + 32 * st + 8 * lq]);
+            af[s][i] = *reinterpret_cast<const bf8_t*>(&As[b][s * MT * LD + a_frag + i * 16 * LD + 32 * st]);
 #pragma unroll
           for (int j = 0; j < FN; ++j)
-            bfr[s][j] = *reinterpret_cast<const bf8_t*>(&Bs[s * NT * LD + (wn * WN + j * 16 + lr) * LD + 32 * st + 8 * lq]);
+            bfr[s][j] = *reinterpret_cast<const bf8_t*>(&Bs[b][s * NT * LD + b_frag + j * 16 * LD + 32 * st]);
         }
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j) {
+            f4_t r = rest[i][j];
             if (ALIGNED) {
+              // lead x lead is exact in float32 and kept apart; nine residual products
               lead[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[0][j], lead[i][j], 0, 0, 0);
-              f4_t r = rest[i][j];
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[1][j], r, 0, 0, 0);
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[0][j], r, 0, 0, 0);
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[2][j], r, 0, 0, 0);
@@ -415,21 +363,19 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[NS - 1][i], bfr[0][j], r, 0, 0, 0);
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[2][j], r, 0, 0, 0);
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2][i], bfr[1][j], r, 0, 0, 0);
-              rest[i][j] = r;
             } else {
-              f4_t r = rest[i][j];
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[0][j], r, 0, 0, 0);
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[1][j], r, 0, 0, 0);
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[0][j], r, 0, 0, 0);
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[2][j], r, 0, 0, 0);
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2][i], bfr[0][j], r, 0, 0, 0);
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[1][j], r, 0, 0, 0);
-              rest[i][j] = r;
             }
+            rest[i][j] = r;
           }
+        if (st == 0) hook();
       }
-      const int kend = kpos_now + kc_now;
-      if (kend % kSplitWindow == 0 || kend >= kext_now) {
+      if (flush) {  // end of a promotion window or of a pair: float32 sums into float64
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -441,9 +387,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
               rest[i][j][r] = 0.f;
             }
       }
-      if (!has1) break;
-      has1 = has2;
-    }
+    };
+    chunk_pipeline<KT, kSplitWindow>(g, pairs, pb, pe, pool, Ap, Bp, w.m0, w.n0, blk.mext, blk.next, store, compute);
   }
   epilogue_f32layout<MT, NT, WM, WN, FM, FN>(pr, w, blk, acc, wm, wn, lr, lq);
 }

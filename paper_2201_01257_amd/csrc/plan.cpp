@@ -3,6 +3,7 @@
 // autotuner that picks kernel configurations by measurement.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -511,8 +512,45 @@ static int default_config(const tamm_plan* p) {
   return best;
 }
 
+// Launch order of the work items for the chip's eight accelerator dies (XCDs), each with its own
+// L2: the dispatcher hands workgroup b to die b % 8.  The longest-first list is cut into chunks of
+// `chunk` consecutive items (neighbouring tiles of one output block, which share operand panels)
+// and chunk c goes to die c % 8, so every die works through whole chunks in longest-first order
+// and tiles that read the same rows of A or columns of B run together behind one L2.  Slots left
+// empty by dies with fewer items are squeezed out, which only moves a few tail items to another
+// die.  A chunk of 0 or 1 keeps the list as it is.
+static void xcd_order(std::vector<WorkItem>& work, int chunk) {
+  constexpr int kDies = 8;
+  const size_t n = work.size();
+  if (chunk <= 1 || n <= (size_t)kDies) return;
+  const size_t nchunks = (n + chunk - 1) / chunk;
+  std::vector<size_t> len(kDies, 0);
+  for (size_t c = 0; c < nchunks; ++c) len[c % kDies] += std::min<size_t>(chunk, n - c * chunk);
+  const size_t rows = *std::max_element(len.begin(), len.end());
+  std::vector<int64_t> slot(rows * kDies, -1);
+  for (int x = 0; x < kDies; ++x)
+    for (size_t i = 0; i < len[x]; ++i) {
+      const size_t c = (size_t)x + kDies * (i / chunk);  // the die's (i / chunk)-th chunk
+      slot[i * kDies + x] = (int64_t)(c * chunk + i % chunk);
+    }
+  std::vector<WorkItem> out;
+  out.reserve(n);
+  for (int64_t l : slot)
+    if (l >= 0) out.push_back(work[(size_t)l]);
+  work.swap(out);
+}
+
+static int xcd_chunk() {
+  static const int v = [] {
+    const char* e = getenv("TAMM_XCD_CHUNK");
+    return e ? std::max(0, atoi(e)) : 32;
+  }();
+  return v;
+}
+
 // Work decomposition for one kernel configuration: macro-tiles of every stored output block,
-// heaviest first (longest-processing-time order), with the K splits of a tile adjacent.
+// heaviest first (longest-processing-time order), with the K splits of a tile adjacent, then laid
+// out for the dies (xcd_order).
 static int configure_work(tamm_plan* p, int config, int k_splits) {
   const int ncfg = cfg_count(p->prec);
   const int64_t nob = (int64_t)p->blocks.size();
@@ -553,6 +591,7 @@ static int configure_work(tamm_plan* p, int config, int k_splits) {
     if (k_splits > 1) p->reduce.push_back(ReduceItem{0, tiles[t].ob, tiles[t].m0, tiles[t].n0, (int32_t)t, 0});
   }
   if (p->work.size() > (size_t)INT32_MAX / 2) return fail(TAMM_ERR_UNSUPPORTED, "too many work items");
+  xcd_order(p->work, xcd_chunk());
   p->config = config;
   p->k_splits = k_splits;
   p->stats.work_items = (int64_t)p->work.size();
