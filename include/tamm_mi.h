@@ -237,8 +237,8 @@ int tamm_group_workspace_size(const tamm_group* g, size_t* bytes);
 /* Bind caller-owned device workspace (256-byte aligned) and upload the members' static tables
  * (synchronous).  Drops a captured graph. */
 int tamm_group_bind_workspace(tamm_group* g, void* dev_ptr, size_t bytes);
-/* Select the kernel configuration (-1 = default) and the persistent grid size (0 = two
- * workgroups per compute unit).  Requires re-querying the workspace size and re-binding. */
+/* Select the kernel configuration (-1 = default) and the persistent grid size (0 = every
+ * resident slot: compute units x workgroups of the configuration that fit on one).  Requires re-querying the workspace size and re-binding. */
 int tamm_group_set_config(tamm_group* g, int32_t config, int32_t grid);
 /* alpha and beta are host arrays of n values, read during the call.  If a graph was captured
  * with the same alpha/beta and the members' storage bindings are unchanged, the graph is
@@ -249,7 +249,7 @@ int tamm_group_execute(tamm_group* g, const double* alpha, const double* beta, v
  * later tamm_group_execute calls with the same values replay it on their stream. */
 int tamm_group_capture(tamm_group* g, const double* alpha, const double* beta, void* stream);
 /* Autotuner for groups: every kernel configuration with persistent grids of 1, 2 and 4
- * workgroups per compute unit, timed on stream with alpha = 0, beta = 1; keeps the fastest and
+ * workgroups per compute unit and the occupancy-sized grid, timed on stream with alpha = 0, beta = 1; keeps the fastest and
  * caches it in cache_path (if non-empty) under the group's structural signature.  Needs a
  * bound workspace large enough for the candidates (candidates that do not fit are skipped).
  * Synchronises the stream. */

@@ -19,6 +19,9 @@ HIPCC_FLAGS = [
     "-shared",
     # packed FP32 instructions are never generated (see the design notes on gfx950 hazards)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in architectural VGPRs: without it the loop-carried accumulators are
+    # copied between VGPRs and AGPRs on every K chunk
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I" + os.path.join(ROOT, "include"),
 ]
 

@@ -225,11 +225,14 @@ struct Gather {
 
 // Chunk pipeline of one work item, shared by the contraction kernels.  LDS holds two chunk
 // buffers and there is one barrier per chunk: while compute(buf, ...) runs the MFMAs of chunk c
-// from buffer `buf`, the hook it calls after its first k-step stores chunk c+1 (in registers
-// since the previous chunk) into the other buffer, issues the global loads of chunk c+2 into the
-// same registers and fetches the table entries of chunk c+3.  `flush` tells compute that chunk c
-// ends a promotion window of W summed indices or a pair (W = 0: pairs only); the flags travel
-// with the chunks in a small FIFO.  Chunks run over pairs [pb, pe) and KT-long pieces of each.
+// from buffer `buf`, the stage() callback it calls after its first k-step stores chunk c+1 (in
+// registers since the previous chunk) into the other buffer and issues the global loads of
+// chunk c+2 into the same registers.  stage() has no branch, so the compiler can interleave its
+// LDS stores and global loads with the MFMAs; past the last chunk it moves data nobody reads.
+// The bookkeeping that does branch (the next chunk's pair, its table entries) runs between the
+// barrier and the next chunk.  `flush` tells compute that chunk c ends a promotion window of W
+// summed indices or a pair (W = 0: pairs only); the flags travel with the chunks in a FIFO.
+// Chunks run over pairs [pb, pe) and KT-long pieces of each.
 template <int KT, int W, typename G, typename T, typename StoreF, typename ComputeF>
 __device__ __forceinline__ void chunk_pipeline(G& g, const PairDesc* pairs, int pb, int pe, const int32_t* pool,
                                                const T* A, const T* B, int m0, int n0, int mext, int next,
@@ -275,21 +278,14 @@ __device__ __forceinline__ void chunk_pipeline(G& g, const PairDesc* pairs, int 
     const bool flush = (fifo & 1u) != 0;
     fifo >>= 1;
     --nf;
-    bool inflight_next = false, tabs_next = false;
     compute(buf, flush, [&]() {
-      if (inflight) {
-        store(buf ^ 1);
-        if (tabs) {
-          g.load_data();
-          inflight_next = true;
-          tabs_next = advance();
-        }
-      }
+      store(buf ^ 1);
+      g.load_data();
     });
     __syncthreads();  // buffer `buf` is free again; the other one holds the next chunk
     if (!inflight) break;
-    inflight = inflight_next;
-    tabs = tabs_next;
+    inflight = tabs;  // the loads just issued carried a real chunk
+    tabs = tabs && advance();
     buf ^= 1;
   }
 }

@@ -153,6 +153,8 @@ const F64Config& f64_config(int id);
 // Launchers (kernels.hip).  Return hipError_t of the launch.  grid <= 0: one workgroup per item.
 hipError_t launch_screen(const ScreenParams& p, hipStream_t s);
 hipError_t launch_contract_f64(int config, int layout, const ContractParams& p, int grid, hipStream_t s);
+// Resident workgroups per compute unit of one configuration and gather layout (at least 1).
+int f64_occupancy(int config, int layout);
 hipError_t launch_reduce(const ReduceParams& p, hipStream_t s);
 hipError_t launch_set_counter(int32_t* counter, int32_t value, hipStream_t s);
 hipError_t launch_denominator(const DenomParams& p, hipStream_t s);

@@ -151,7 +151,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f64(ContractParams 
 #pragma unroll
         for (int e = 0; e < G::BE; ++e) Bs[b][g.b_lds_row(e) * LD + g.b_lds_k(e)] = g.rb[e];
       };
-      auto compute = [&](int b, bool, auto&& hook) {
+      auto compute = [&](int b, bool, auto&& stage) {
         const double* as = As[b] + a_frag;
         const double* bs = Bs[b] + b_frag;
         double af[2][FM], bf[2][FN];
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f64(ContractParams 
 #pragma unroll
             for (int j = 0; j < FN; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[cur][i], bf[cur][j], acc[i][j], 0, 0, 0);
-          if (s == 0) hook();
+          if (s == 0) stage();
         }
       };
       chunk_pipeline<KT, 0>(g, pairs, pb, pe, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next, store, compute);
@@ -285,6 +285,37 @@ static hipError_t launch_cfg(int layout, const ContractParams& p, int grid, hipS
     default: hipLaunchKernelGGL((k_contract_f64<MT, NT, KT, WGM, WGN, false, false>), g, b, 0, s, p); break;
   }
   return hipGetLastError();
+}
+
+template <int MT, int NT, int KT, int WGM, int WGN>
+static int occupancy_cfg(int layout) {
+  int n = 0;
+  const int threads = 64 * WGM * WGN;
+  hipError_t e;
+  switch (layout) {
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, true, true>, threads, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, true, false>, threads, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, false, true>, threads, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, false, false>, threads, 0); break;
+  }
+  return e == hipSuccess && n > 0 ? n : 1;
+}
+
+int f64_occupancy(int config, int layout) {
+  switch (config) {
+    case 0: return occupancy_cfg<64, 64, 16, 2, 2>(layout);
+    case 1: return occupancy_cfg<128, 64, 16, 2, 2>(layout);
+    case 2: return occupancy_cfg<64, 128, 16, 2, 2>(layout);
+    case 3: return occupancy_cfg<128, 128, 16, 2, 2>(layout);
+    case 4: return occupancy_cfg<32, 64, 16, 2, 2>(layout);
+    case 5: return occupancy_cfg<128, 80, 16, 4, 1>(layout);
+    case 6: return occupancy_cfg<80, 128, 16, 1, 4>(layout);
+    case 7: return occupancy_cfg<64, 80, 16, 4, 1>(layout);
+    case 8: return occupancy_cfg<32, 256, 16, 1, 4>(layout);
+    case 9: return occupancy_cfg<256, 32, 16, 4, 1>(layout);
+    case 10: return occupancy_cfg<128, 128, 32, 2, 2>(layout);
+    default: return 1;
+  }
 }
 
 hipError_t launch_contract_f64(int config, int layout, const ContractParams& p, int grid, hipStream_t s) {

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
 #pragma unroll
       for (int e = 0; e < G::BE; ++e) Bs[b][g.b_lds_row(e) * LD + g.b_lds_k(e)] = (float)g.rb[e];
     };
-    auto compute = [&](int b, bool flush, auto&& hook) {
+    auto compute = [&](int b, bool flush, auto&& stage) {
       const float* as = As[b] + a_frag;
       const float* bs = Bs[b] + b_frag;
       float af[2][FM], bf[2][FN];
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
 #pragma unroll
           for (int j = 0; j < FN; ++j)
             part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[cur][i], bf[cur][j], part[i][j], 0, 0, 0);
-        if (s == 0) hook();
+        if (s == 0) stage();
       }
       if (flush) {  // end of a promotion window or of a pair: float32 sums into float64
 #pragma unroll
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
         for (int s = 0; s < NS; ++s) Bs16[s * NT * LD + o] = (unsigned short)(g.rb[e] >> (16 * s));
       }
     };
-    auto compute = [&](int b, bool flush, auto&& hook) {
+    auto compute = [&](int b, bool flush, auto&& stage) {
 #pragma unroll
       for (int st = 0; st < KT / 32; ++st) {  // zeros beyond a ragged chunk's K extent
         bf8_t af[NS][FM], bfr[NS][FN];
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
             }
             rest[i][j] = r;
           }
-        if (st == 0) hook();
+        if (st == 0) stage();
       }
       if (flush) {  // end of a promotion window or of a pair: float32 sums into float64
 #pragma unroll

@@ -1078,14 +1078,16 @@ extern "C" int tamm_group_set_config(tamm_group* g, int32_t config, int32_t grid
   return ok();
 }
 
-static int group_grid(const tamm_group* g, int n_work) {
+// Persistent grid of one layout class: the tuned size, else every resident slot of the device
+// (compute units x resident workgroups of the configuration).
+static int group_grid(const tamm_group* g, int layout, int n_work) {
   if (g->grid > 0) return std::max(1, std::min<int>(g->grid, n_work));
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
   }
-  return std::max(1, std::min<int>(2 * cus, n_work));
+  return std::max(1, std::min<int>(f64_occupancy(g->config, layout) * cus, n_work));
 }
 
 // Enqueue the group's kernels (counter reset, screening, persistent contraction).
@@ -1100,7 +1102,7 @@ static int group_enqueue(tamm_group* g, hipStream_t s) {
   for (int c = 0; c < 4; ++c) {
     const int n = g->cls_begin[c + 1] - g->cls_begin[c];
     if (n <= 0) continue;
-    const int grid = group_grid(g, n);
+    const int grid = group_grid(g, c, n);
     int32_t* counter = (int32_t*)(g->ws + g->off_counter) + c;
     HIP_TRY(launch_set_counter(counter, grid, s));
     ContractParams cp{};
@@ -1234,7 +1236,7 @@ extern "C" int tamm_group_autotune(tamm_group* g, void* stream, const char* cach
     int cus = 256, dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     for (int c = 0; c < f64_config_count() && rc == TAMM_OK; ++c) {
-      for (int mult : {1, 2, 4}) {
+      for (int mult : {0, 1, 2, 4}) {  // 0: every resident slot (occupancy-sized grid)
         if ((rc = group_configure(g, c)) != TAMM_OK) break;
         if (g->ws_size > bytes) continue;
         g->grid = mult * cus;
