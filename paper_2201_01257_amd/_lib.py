@@ -108,19 +108,21 @@ def header_functions():
 
 
 def load():
-    """Load the in-tree HIP library; raise if it has not been built (there is no fallback)."""
+    """Load the HIP library (the in-tree build, or the file named by TAMM_MI_LIBRARY); raise if it
+    does not exist (there is no fallback)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        path = os.environ.get("TAMM_MI_LIBRARY") or LIB_PATH
+        if not os.path.exists(path):
             raise RuntimeError(
-                f"{LIB_PATH} is missing: build the HIP library first (python -m paper_2201_01257_amd.build)")
+                f"{path} is missing: build the HIP library first (python -m paper_2201_01257_amd.build)")
         # The library resolves libamdhip64.so.7 by soname.  torch ships its own HIP runtime under
         # that soname; loading torch first makes both use that single runtime instead of two.
         try:
             import torch  # noqa: F401
         except ImportError:  # pragma: no cover - C-only use without torch
             pass
-        lib = ctypes.CDLL(LIB_PATH)
+        lib = ctypes.CDLL(path)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(lib, name)
             f.restype = res

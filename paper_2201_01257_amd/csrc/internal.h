@@ -143,7 +143,7 @@ struct DenomParams {
 
 // Kernel configuration of the FP64 contraction kernel family.
 struct F64Config {
-  int mt, nt, kt, wgm, wgn;
+  int mt, nt, kt, wgm, wgn, occ;  // occ: minimum waves per SIMD the registers must allow
   const char* name;
 };
 

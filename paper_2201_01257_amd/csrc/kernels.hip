@@ -101,8 +101,8 @@ hipError_t launch_screen(const ScreenParams& p, hipStream_t s) {
 // from a counter (the grouped launch); the item order is the plan's.  The operands' gather
 // layouts (A_KC, B_KC) are template parameters: "layout" = 2*A_KC + B_KC.
 // ---------------------------------------------------------------------------------------------
-template <int MT, int NT, int KT, int WGM, int WGN, bool A_KC, bool B_KC>
-__global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f64(ContractParams P) {
+template <int MT, int NT, int KT, int WGM, int WGN, int OCC, bool A_KC, bool B_KC>
+__global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(OCC))) void k_contract_f64(ContractParams P) {
   constexpr int NTHR = 64 * WGM * WGN;
   constexpr int WM = MT / WGM, WN = NT / WGN;
   constexpr int FM = WM / 16, FN = WN / 16;
@@ -159,6 +159,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f64(ContractParams 
         for (int i = 0; i < FM; ++i) af[0][i] = as[i * 16 * LD];
 #pragma unroll
         for (int j = 0; j < FN; ++j) bf[0][j] = bs[j * 16 * LD];
+        __builtin_amdgcn_s_setprio(1);  // MFMA phase first when waves of two workgroups compete
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
           const int cur = s & 1, nxt = cur ^ 1;
@@ -175,6 +176,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f64(ContractParams 
               acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[cur][i], bf[cur][j], acc[i][j], 0, 0, 0);
           if (s == 0) stage();
         }
+        __builtin_amdgcn_s_setprio(0);
       };
       chunk_pipeline<KT, 0>(g, pairs, pb, pe, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next, store, compute);
     }
@@ -256,64 +258,65 @@ hipError_t launch_reduce(const ReduceParams& p, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Configurations and dispatch
+// Configurations and dispatch.  X(id, MT, NT, KT, WGM, WGN, OCC): OCC is the minimum number of
+// waves per SIMD the register allocation must allow (1 = no constraint).
 // ---------------------------------------------------------------------------------------------
-static const F64Config kF64Configs[] = {
-    {64, 64, 16, 2, 2, "f64_m64n64k16_w2x2"},
-    {128, 64, 16, 2, 2, "f64_m128n64k16_w2x2"},
-    {64, 128, 16, 2, 2, "f64_m64n128k16_w2x2"},
-    {128, 128, 16, 2, 2, "f64_m128n128k16_w2x2"},
-    {32, 64, 16, 2, 2, "f64_m32n64k16_w2x2"},
-    {128, 80, 16, 4, 1, "f64_m128n80k16_w4x1"},
-    {80, 128, 16, 1, 4, "f64_m80n128k16_w1x4"},
-    {64, 80, 16, 4, 1, "f64_m64n80k16_w4x1"},
-    {32, 256, 16, 1, 4, "f64_m32n256k16_w1x4"},
-    {256, 32, 16, 4, 1, "f64_m256n32k16_w4x1"},
-    {128, 128, 32, 2, 2, "f64_m128n128k32_w2x2"},
-};
+#define TAMM_F64_CONFIGS(X)            \
+  X(0, 64, 64, 16, 2, 2, 1)            \
+  X(1, 128, 64, 16, 2, 2, 1)           \
+  X(2, 64, 128, 16, 2, 2, 1)           \
+  X(3, 128, 128, 16, 2, 2, 1)          \
+  X(4, 32, 64, 16, 2, 2, 1)            \
+  X(5, 128, 80, 16, 4, 1, 1)           \
+  X(6, 80, 128, 16, 1, 4, 1)           \
+  X(7, 64, 80, 16, 4, 1, 1)            \
+  X(8, 32, 256, 16, 1, 4, 1)           \
+  X(9, 256, 32, 16, 4, 1, 1)           \
+  X(10, 128, 128, 32, 2, 2, 1)         \
+  X(11, 128, 80, 32, 4, 1, 1)          \
+  X(12, 64, 80, 32, 4, 1, 1)           \
+  X(13, 64, 64, 32, 2, 2, 1)
+
+#define TAMM_CFG_ENTRY(id, mt, nt, kt, wgm, wgn, occ) \
+  {mt, nt, kt, wgm, wgn, occ, "f64_m" #mt "n" #nt "k" #kt "_w" #wgm "x" #wgn "_o" #occ},
+static const F64Config kF64Configs[] = {TAMM_F64_CONFIGS(TAMM_CFG_ENTRY)};
+#undef TAMM_CFG_ENTRY
 
 int f64_config_count() { return (int)(sizeof(kF64Configs) / sizeof(kF64Configs[0])); }
 const F64Config& f64_config(int id) { return kF64Configs[id]; }
 
-template <int MT, int NT, int KT, int WGM, int WGN>
+template <int MT, int NT, int KT, int WGM, int WGN, int OCC>
 static hipError_t launch_cfg(int layout, const ContractParams& p, int grid, hipStream_t s) {
   const dim3 g(grid > 0 ? grid : p.n_work), b(64 * WGM * WGN);
   switch (layout) {
-    case 3: hipLaunchKernelGGL((k_contract_f64<MT, NT, KT, WGM, WGN, true, true>), g, b, 0, s, p); break;
-    case 2: hipLaunchKernelGGL((k_contract_f64<MT, NT, KT, WGM, WGN, true, false>), g, b, 0, s, p); break;
-    case 1: hipLaunchKernelGGL((k_contract_f64<MT, NT, KT, WGM, WGN, false, true>), g, b, 0, s, p); break;
-    default: hipLaunchKernelGGL((k_contract_f64<MT, NT, KT, WGM, WGN, false, false>), g, b, 0, s, p); break;
+    case 3: hipLaunchKernelGGL((k_contract_f64<MT, NT, KT, WGM, WGN, OCC, true, true>), g, b, 0, s, p); break;
+    case 2: hipLaunchKernelGGL((k_contract_f64<MT, NT, KT, WGM, WGN, OCC, true, false>), g, b, 0, s, p); break;
+    case 1: hipLaunchKernelGGL((k_contract_f64<MT, NT, KT, WGM, WGN, OCC, false, true>), g, b, 0, s, p); break;
+    default: hipLaunchKernelGGL((k_contract_f64<MT, NT, KT, WGM, WGN, OCC, false, false>), g, b, 0, s, p); break;
   }
   return hipGetLastError();
 }
 
-template <int MT, int NT, int KT, int WGM, int WGN>
+template <int MT, int NT, int KT, int WGM, int WGN, int OCC>
 static int occupancy_cfg(int layout) {
   int n = 0;
   const int threads = 64 * WGM * WGN;
   hipError_t e;
   switch (layout) {
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, true, true>, threads, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, true, false>, threads, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, false, true>, threads, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, false, false>, threads, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, OCC, true, true>, threads, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, OCC, true, false>, threads, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, OCC, false, true>, threads, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, OCC, false, false>, threads, 0); break;
   }
   return e == hipSuccess && n > 0 ? n : 1;
 }
 
 int f64_occupancy(int config, int layout) {
   switch (config) {
-    case 0: return occupancy_cfg<64, 64, 16, 2, 2>(layout);
-    case 1: return occupancy_cfg<128, 64, 16, 2, 2>(layout);
-    case 2: return occupancy_cfg<64, 128, 16, 2, 2>(layout);
-    case 3: return occupancy_cfg<128, 128, 16, 2, 2>(layout);
-    case 4: return occupancy_cfg<32, 64, 16, 2, 2>(layout);
-    case 5: return occupancy_cfg<128, 80, 16, 4, 1>(layout);
-    case 6: return occupancy_cfg<80, 128, 16, 1, 4>(layout);
-    case 7: return occupancy_cfg<64, 80, 16, 4, 1>(layout);
-    case 8: return occupancy_cfg<32, 256, 16, 1, 4>(layout);
-    case 9: return occupancy_cfg<256, 32, 16, 4, 1>(layout);
-    case 10: return occupancy_cfg<128, 128, 32, 2, 2>(layout);
+#define TAMM_CFG_OCC(id, mt, nt, kt, wgm, wgn, occ) \
+  case id: return occupancy_cfg<mt, nt, kt, wgm, wgn, occ>(layout);
+    TAMM_F64_CONFIGS(TAMM_CFG_OCC)
+#undef TAMM_CFG_OCC
     default: return 1;
   }
 }
@@ -321,66 +324,93 @@ int f64_occupancy(int config, int layout) {
 hipError_t launch_contract_f64(int config, int layout, const ContractParams& p, int grid, hipStream_t s) {
   if (p.n_work <= 0) return hipSuccess;
   switch (config) {
-    case 0: return launch_cfg<64, 64, 16, 2, 2>(layout, p, grid, s);
-    case 1: return launch_cfg<128, 64, 16, 2, 2>(layout, p, grid, s);
-    case 2: return launch_cfg<64, 128, 16, 2, 2>(layout, p, grid, s);
-    case 3: return launch_cfg<128, 128, 16, 2, 2>(layout, p, grid, s);
-    case 4: return launch_cfg<32, 64, 16, 2, 2>(layout, p, grid, s);
-    case 5: return launch_cfg<128, 80, 16, 4, 1>(layout, p, grid, s);
-    case 6: return launch_cfg<80, 128, 16, 1, 4>(layout, p, grid, s);
-    case 7: return launch_cfg<64, 80, 16, 4, 1>(layout, p, grid, s);
-    case 8: return launch_cfg<32, 256, 16, 1, 4>(layout, p, grid, s);
-    case 9: return launch_cfg<256, 32, 16, 4, 1>(layout, p, grid, s);
-    case 10: return launch_cfg<128, 128, 32, 2, 2>(layout, p, grid, s);
+#define TAMM_CFG_LAUNCH(id, mt, nt, kt, wgm, wgn, occ) \
+  case id: return launch_cfg<mt, nt, kt, wgm, wgn, occ>(layout, p, grid, s);
+    TAMM_F64_CONFIGS(TAMM_CFG_LAUNCH)
+#undef TAMM_CFG_LAUNCH
     default: return hipErrorInvalidValue;
   }
 }
 
 // ---------------------------------------------------------------------------------------------
 // Orbital-energy denominator update.  Each workgroup handles `chunk` consecutive elements of one
-// stored block; IEEE float64 division; the denominator is summed in the documented order.
+// stored block; IEEE float64 division; the denominator is summed in the documented order (the
+// energies of the +1 dimensions in dimension order, then minus those of the -1 dimensions).
+// A thread splits its first element into per-dimension indices once and then steps by the
+// workgroup size with a mixed-radix add, so no integer division runs per element.
 // ---------------------------------------------------------------------------------------------
+template <int RANK>
+__device__ __forceinline__ void denominator_block(const DenomParams& P, int b, int e0, int e1) {
+  int lo[RANK], ext[RANK], idx[RANK], step[RANK];
+#pragma unroll
+  for (int d = 0; d < RANK; ++d) {
+    const int t = P.block_tiles[(int64_t)b * RANK + d];
+    lo[d] = (int)P.tile_offset[P.dim_tile_base[d] + t];
+    ext[d] = (int)P.tile_size[P.dim_tile_base[d] + t];
+  }
+  int rem = e0 + (int)threadIdx.x, srem = (int)blockDim.x;
+#pragma unroll
+  for (int d = RANK - 1; d >= 0; --d) {
+    idx[d] = rem % ext[d];
+    rem /= ext[d];
+    step[d] = srem % ext[d];
+    srem /= ext[d];
+  }
+  const int64_t base = P.block_off[b];
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += (int)blockDim.x) {
+    double den = 0.0;
+    bool first = true;
+#pragma unroll
+    for (int d = 0; d < RANK; ++d)
+      if (P.sign[d] > 0) {
+        const double v = P.energy[d][lo[d] + idx[d]];
+        den = first ? v : den + v;
+        first = false;
+      }
+#pragma unroll
+    for (int d = 0; d < RANK; ++d)
+      if (P.sign[d] < 0) {
+        const double v = P.energy[d][lo[d] + idx[d]];
+        den = first ? -v : den - v;
+        first = false;
+      }
+    P.out[base + e] = P.in[base + e] / den;
+    int carry = 0;  // idx += step in the block's mixed radix (each digit stays below 2*ext)
+#pragma unroll
+    for (int d = RANK - 1; d >= 0; --d) {
+      idx[d] += step[d] + carry;
+      carry = idx[d] >= ext[d] ? 1 : 0;
+      idx[d] -= carry ? ext[d] : 0;
+    }
+  }
+}
+
+template <int RANK>
 __global__ __launch_bounds__(256) void k_denominator(DenomParams P) {
   const int64_t it = blockIdx.x;
   if (it >= P.n_items) return;
   const int b = P.item_block[it];
-  const int rank = P.rank;
-  int lo[kMaxRank], ext[kMaxRank];
   int n = 1;
-  for (int d = 0; d < rank; ++d) {
-    const int t = P.block_tiles[(int64_t)b * rank + d];
-    lo[d] = (int)P.tile_offset[P.dim_tile_base[d] + t];
-    ext[d] = (int)P.tile_size[P.dim_tile_base[d] + t];
-    n *= ext[d];
-  }
-  const int64_t base = P.block_off[b];
+#pragma unroll
+  for (int d = 0; d < RANK; ++d) n *= (int)P.tile_size[P.dim_tile_base[d] + P.block_tiles[(int64_t)b * RANK + d]];
   const int e0 = P.item_start[it];
-  const int e1 = min(n, e0 + P.chunk);
-  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    int rem = e, idx[kMaxRank];
-    for (int d = rank - 1; d >= 0; --d) {
-      idx[d] = lo[d] + rem % ext[d];
-      rem /= ext[d];
-    }
-    double den = 0.0;
-    bool first = true;
-    for (int d = 0; d < rank; ++d)
-      if (P.sign[d] > 0) {
-        den = first ? P.energy[d][idx[d]] : den + P.energy[d][idx[d]];
-        first = false;
-      }
-    for (int d = 0; d < rank; ++d)
-      if (P.sign[d] < 0) {
-        den = first ? -P.energy[d][idx[d]] : den - P.energy[d][idx[d]];
-        first = false;
-      }
-    P.out[base + e] = P.in[base + e] / den;
-  }
+  denominator_block<RANK>(P, b, e0, min(n, e0 + P.chunk));
 }
 
 hipError_t launch_denominator(const DenomParams& p, hipStream_t s) {
   if (p.n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_denominator, dim3((unsigned)p.n_items), dim3(256), 0, s, p);
+  const dim3 g((unsigned)p.n_items), blk(256);
+  switch (p.rank) {
+    case 1: hipLaunchKernelGGL(k_denominator<1>, g, blk, 0, s, p); break;
+    case 2: hipLaunchKernelGGL(k_denominator<2>, g, blk, 0, s, p); break;
+    case 3: hipLaunchKernelGGL(k_denominator<3>, g, blk, 0, s, p); break;
+    case 4: hipLaunchKernelGGL(k_denominator<4>, g, blk, 0, s, p); break;
+    case 5: hipLaunchKernelGGL(k_denominator<5>, g, blk, 0, s, p); break;
+    case 6: hipLaunchKernelGGL(k_denominator<6>, g, blk, 0, s, p); break;
+    case 7: hipLaunchKernelGGL(k_denominator<7>, g, blk, 0, s, p); break;
+    case 8: hipLaunchKernelGGL(k_denominator<8>, g, blk, 0, s, p); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

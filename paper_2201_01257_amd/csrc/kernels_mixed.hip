@@ -237,6 +237,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
       for (int i = 0; i < FM; ++i) af[0][i] = as[i * 16 * LD];
 #pragma unroll
       for (int j = 0; j < FN; ++j) bf[0][j] = bs[j * 16 * LD];
+      __builtin_amdgcn_s_setprio(1);  // MFMA phase first when waves of two workgroups compete
 #pragma unroll
       for (int s = 0; s < KT / 4; ++s) {  // zeros beyond a ragged chunk's K extent
         const int cur = s & 1, nxt = cur ^ 1;
@@ -253,6 +254,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
             part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[cur][i], bf[cur][j], part[i][j], 0, 0, 0);
         if (s == 0) stage();
       }
+      __builtin_amdgcn_s_setprio(0);
       if (flush) {  // end of a promotion window or of a pair: float32 sums into float64
 #pragma unroll
         for (int i = 0; i < FM; ++i)
@@ -334,6 +336,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
       }
     };
     auto compute = [&](int b, bool flush, auto&& stage) {
+      __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int st = 0; st < KT / 32; ++st) {  // zeros beyond a ragged chunk's K extent
         bf8_t af[NS][FM], bfr[NS][FN];
@@ -375,6 +378,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
           }
         if (st == 0) stage();
       }
+      __builtin_amdgcn_s_setprio(0);
       if (flush) {  // end of a promotion window or of a pair: float32 sums into float64
 #pragma unroll
         for (int i = 0; i < FM; ++i)
