@@ -37,8 +37,41 @@ PEAK_F64_MFMA_TFLOPS = 78.6
 STEP_TERMS = ["hh_int", "ladder", "ring", "hh", "t1_v", "t1_o"]
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "ladder_hbm_traffic.json")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    """sha256 over the library's HIP/C++ sources and public header: identifies the kernels that a
+    stored counter measurement was taken on."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2201_01257_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".h", ".cpp")))
+    for f in files + [os.path.join(ROOT, "include", "tamm_mi.h")]:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, config_name: str, work_items: int):
+    """HBM bytes per launch of the ladder contraction (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+    from the committed counter record, if it was taken on these kernel sources with the same
+    configuration and work decomposition; otherwise None."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if (rec.get("source_sha256") != kernel_source_digest() or rec.get("workload") != workload
+            or rec.get("config") != config_name or rec.get("work_items") != work_items):
+        return None
+    return int(rec["hbm_bytes_per_launch"])
 
 
 def build_inputs(torch, tm, synth, wl):
@@ -190,7 +223,9 @@ def main():
     lad_ms = acc["ladder_kernel"] / args.steps
     achieved = flops["ladder"] / (lad_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_F64_MFMA_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_F64_MFMA_TFLOPS, 4),
+                "traffic": measured_traffic(args.workload, plans["ladder"].config_name(),
+                                            plans["ladder"].stats()["work_items"]),
                 "kernel": "k_contract_f64 (ladder, " + plans["ladder"].config_name() + ")",
                 "kernel_ms": round(lad_ms, 4)}
 

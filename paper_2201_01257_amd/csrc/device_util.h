@@ -8,12 +8,9 @@
 
 namespace tamm {
 
-// Byte offset that lies outside every block range used with the buffer loads below: a raw
-// buffer load whose offset is at or beyond the resource's size returns zero (no memory access),
-// which is how padding rows, columns and k positions read as zeros without branches.
-constexpr uint32_t kOutOfRange = 0x40000000u;
-// Largest block the gathers address through one buffer resource (bytes, exclusive).
-constexpr int64_t kMaxBlockBytes = (int64_t)kOutOfRange;
+// Largest block the gathers address through one buffer resource (bytes, exclusive): every table
+// sum that involves kTableInvalid lands at or beyond it.
+constexpr int64_t kMaxBlockBytes = (int64_t)kTableInvalid * 8;
 
 // Loads through explicit address spaces: per-lane table reads as global loads (not flat), and
 // wave-uniform descriptor reads as scalar loads from the constant address space (the descriptors
@@ -124,10 +121,10 @@ namespace tamm {
 // count divides the thread count a thread keeps one row and AE (BE) k positions; otherwise
 // (e.g. 80 rows, 256 threads) every element has its own row and k.
 //
-// Everything is branch-free: table entries are fetched at clamped (always valid) positions and
-// their validity is kept aside; the data load of an invalid element uses kOutOfRange as its byte
-// offset and the buffer hardware returns zero.  Table entries are fetched a chunk ahead of the
-// data, so no dependent table->data chain sits in front of the MFMAs.
+// Everything is branch-free: rows, columns and k positions outside the block read the padding
+// entries of the offset tables (kTableInvalid), whose element offset is beyond the buffer
+// resource, and the buffer hardware returns zero for them.  Table entries are fetched a chunk
+// ahead of the data, so no dependent table->data chain sits in front of the MFMAs.
 template <int R, int KT, int NTHR, bool KC>
 struct GatherMap {
   static constexpr int E = R * KT / NTHR;                       // elements per thread
@@ -136,7 +133,6 @@ struct GatherMap {
   static constexpr int NK = KC ? 1 : E;                         // distinct k-table entries
   static_assert(R * KT % NTHR == 0, "chunk elements must split evenly over the threads");
   static_assert(!KC || (NTHR % KT == 0 && R % (NTHR / KT) == 0), "k-contiguous gather mapping");
-  static_assert(E <= 32, "validity masks hold 32 elements");
   __device__ static int row(int tid, int e) { return KC ? tid / KT + e * (NTHR / KT) : (tid + e * NTHR) % R; }
   __device__ static int k(int tid, int e) { return KC ? tid % KT : (tid + e * NTHR) / R; }
   __device__ static int ridx(int e) { return KC ? e : (ROW_FIXED ? 0 : e); }  // row entry of element e
@@ -154,9 +150,8 @@ struct Gather {
   const T* a_base;                        // current pair's operand blocks
   const T* b_base;
   uint32_t a_bytes, b_bytes;
-  int a_rt[A_NR], b_rt[B_NR];             // row table entries (elements)
-  int a_kt[A_NK], b_kt[B_NK];             // k table entries (elements)
-  uint32_t a_rok, b_rok, a_kok, b_kok;    // validity bits
+  int a_rt[A_NR], b_rt[B_NR];             // row table entries (elements; kTableInvalid past the block)
+  int a_kt[A_NK], b_kt[B_NK];             // k table entries (elements; kTableInvalid past the block)
   T ra[AE], rb[BE];
 
   __device__ void init(int t) { tid = t; }
@@ -166,55 +161,25 @@ struct Gather {
     b_base = B + d.b_off;
     a_bytes = (uint32_t)((int64_t)mext * d.kext * 8);
     b_bytes = (uint32_t)((int64_t)next * d.kext * 8);
-    a_rok = 0;
-    b_rok = 0;
 #pragma unroll
-    for (int e = 0; e < A_NR; ++e) {
-      const int m = m0 + MA::row(tid, e);
-      a_rt[e] = gload(pool + d.a_tabM + min(m, mext - 1));
-      a_rok |= (m < mext ? 1u : 0u) << e;
-    }
+    for (int e = 0; e < A_NR; ++e) a_rt[e] = gload(pool + d.a_tabM + m0 + MA::row(tid, e));
 #pragma unroll
-    for (int e = 0; e < B_NR; ++e) {
-      const int n = n0 + MB::row(tid, e);
-      b_rt[e] = gload(pool + d.b_tabN + min(n, next - 1));
-      b_rok |= (n < next ? 1u : 0u) << e;
-    }
+    for (int e = 0; e < B_NR; ++e) b_rt[e] = gload(pool + d.b_tabN + n0 + MB::row(tid, e));
   }
   __device__ void load_tables(const PairDesc& d, const int32_t* pool, int kbase) {
-    a_kok = 0;
-    b_kok = 0;
 #pragma unroll
-    for (int e = 0; e < A_NK; ++e) {
-      const int k = kbase + MA::k(tid, e);
-      a_kt[e] = gload(pool + d.a_tabK + min(k, d.kext - 1));
-      a_kok |= (k < d.kext ? 1u : 0u) << e;
-    }
+    for (int e = 0; e < A_NK; ++e) a_kt[e] = gload(pool + d.a_tabK + kbase + MA::k(tid, e));
 #pragma unroll
-    for (int e = 0; e < B_NK; ++e) {
-      const int k = kbase + MB::k(tid, e);
-      b_kt[e] = gload(pool + d.b_tabK + min(k, d.kext - 1));
-      b_kok |= (k < d.kext ? 1u : 0u) << e;
-    }
+    for (int e = 0; e < B_NK; ++e) b_kt[e] = gload(pool + d.b_tabK + kbase + MB::k(tid, e));
   }
   __device__ void load_data() {
     // resources built here from wave-uniform values, so that they live in scalar registers
     const __amdgpu_buffer_rsrc_t a_rsrc = block_rsrc(a_base, a_bytes);
     const __amdgpu_buffer_rsrc_t b_rsrc = block_rsrc(b_base, b_bytes);
 #pragma unroll
-    for (int e = 0; e < AE; ++e) {
-      const int er = MA::ridx(e), ek = MA::kidx(e);
-      const bool ok = ((a_rok >> er) & (a_kok >> ek) & 1u) != 0;
-      const uint32_t off = ok ? (uint32_t)(a_rt[er] + a_kt[ek]) * 8u : kOutOfRange;
-      ra[e] = buffer_load8<T>(a_rsrc, off);
-    }
+    for (int e = 0; e < AE; ++e) ra[e] = buffer_load8<T>(a_rsrc, (uint32_t)(a_rt[MA::ridx(e)] + a_kt[MA::kidx(e)]) * 8u);
 #pragma unroll
-    for (int e = 0; e < BE; ++e) {
-      const int er = MB::ridx(e), ek = MB::kidx(e);
-      const bool ok = ((b_rok >> er) & (b_kok >> ek) & 1u) != 0;
-      const uint32_t off = ok ? (uint32_t)(b_rt[er] + b_kt[ek]) * 8u : kOutOfRange;
-      rb[e] = buffer_load8<T>(b_rsrc, off);
-    }
+    for (int e = 0; e < BE; ++e) rb[e] = buffer_load8<T>(b_rsrc, (uint32_t)(b_rt[MB::ridx(e)] + b_kt[MB::kidx(e)]) * 8u);
   }
   __device__ int a_lds_row(int e) const { return MA::row(tid, e); }
   __device__ int a_lds_k(int e) const { return MA::k(tid, e); }

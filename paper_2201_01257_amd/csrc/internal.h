@@ -8,6 +8,14 @@ namespace tamm {
 
 constexpr int kMaxRank = 8;
 
+// Operand offset tables are followed by kTablePad entries holding kTableInvalid, so that the
+// gathers may read a table up to a tile (or a K chunk) past its end.  A gathered element whose
+// row or k entry is kTableInvalid lies at least 8 * kTableInvalid bytes = 1 GiB into its block,
+// which is beyond every operand block (the planner rejects blocks of 2^27 or more elements), so
+// the bounds-checked buffer load returns zero for it.
+constexpr int32_t kTableInvalid = 1 << 27;
+constexpr int kTablePad = 256;
+
 // One stored block of the output tensor, as the contraction kernel and the screening kernel see
 // it.  The flattened M (out&A) and N (out&B) extents and the offset tables that map a flattened
 // row/column to an element offset inside the block are fixed by the block's tile sizes.

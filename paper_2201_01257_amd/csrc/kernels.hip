@@ -275,7 +275,8 @@ hipError_t launch_reduce(const ReduceParams& p, hipStream_t s) {
   X(10, 128, 128, 32, 2, 2, 1)         \
   X(11, 128, 80, 32, 4, 1, 1)          \
   X(12, 64, 80, 32, 4, 1, 1)           \
-  X(13, 64, 64, 32, 2, 2, 1)
+  X(13, 64, 64, 32, 2, 2, 1)           \
+  X(14, 128, 128, 16, 2, 2, 2)
 
 #define TAMM_CFG_ENTRY(id, mt, nt, kt, wgm, wgn, occ) \
   {mt, nt, kt, wgm, wgn, occ, "f64_m" #mt "n" #nt "k" #kt "_w" #wgm "x" #wgn "_o" #occ},

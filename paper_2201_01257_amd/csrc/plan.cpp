@@ -33,6 +33,13 @@ int32_t pool_push(std::vector<int32_t>& pool, const std::vector<int64_t>& v) {
   return start;
 }
 
+// An offset table followed by its padding of invalid entries (read by the gathers past the end).
+static int32_t pool_push_table(std::vector<int32_t>& pool, const std::vector<int64_t>& v) {
+  const int32_t start = pool_push(pool, v);
+  pool.insert(pool.end(), kTablePad, kTableInvalid);
+  return start;
+}
+
 // Offset table of one label group inside blocks of one operand shape: flattened index (mixed
 // radix over `group`, last fastest) -> element offset in the row-major block.
 std::vector<int64_t> group_table(const std::vector<int>& group, const std::vector<int64_t>& lab_ext,
@@ -294,12 +301,14 @@ extern "C" int tamm_plan_create(tamm_tensor* out, const char* out_lbl, const tam
         stride *= L.cls_size[cl];
       }
       if (stride > INT32_MAX) return false;
-      start1[c] = pool_push(pool, group_table(g1, lab_ext, lab_stride));
-      start2[c] = pool_push(pool, group_table(g2, lab_ext, lab_stride));
+      start1[c] = pool_push_table(pool, group_table(g1, lab_ext, lab_stride));
+      start2[c] = pool_push_table(pool, group_table(g2, lab_ext, lab_stride));
       if (pool.size() > (size_t)INT32_MAX / 2) return false;
     }
     return true;
   };
+  if (p->A->max_block >= kTableInvalid || p->B->max_block >= kTableInvalid)
+    return fail(TAMM_ERR_UNSUPPORTED, "operand blocks of 2^27 or more elements are not supported");
   std::vector<int64_t> aM, aK, bK, bN, oM, oN;
   if (!build_tables(ai, p->M, p->K, aM, aK) || !build_tables(bi, p->K, p->N, bK, bN) || !build_tables(oi, p->M, p->N, oM, oN))
     return fail(TAMM_ERR_UNSUPPORTED, "a block has more than 2^31 elements or the offset tables are too large");
