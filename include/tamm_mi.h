@@ -177,6 +177,12 @@ typedef struct {
   int64_t work_items;     /* output macro-tiles times K splits scheduled by the kernel         */
   int32_t kernel_config;  /* active kernel configuration id                                    */
   int32_t k_splits;       /* K splits per output macro-tile                                    */
+  int32_t gather_layout;  /* the operand holding out's last label is B, the other A.
+                             bit 1: A's stride-1 label is summed (lanes gather along k);
+                             bit 0: the same for B; bit 2: every pair of offset-table entries
+                             the gathers group is adjacent in memory, so the float64 kernels
+                             load two elements per lane (16-byte loads)                        */
+  int32_t reserved;       /* zero                                                              */
 } tamm_plan_stats;
 
 int tamm_plan_stats_get(const tamm_plan* p, tamm_plan_stats* s);

@@ -28,6 +28,8 @@ class PlanStats(ctypes.Structure):
         ("work_items", c_i64),
         ("kernel_config", c_i32),
         ("k_splits", c_i32),
+        ("gather_layout", c_i32),
+        ("reserved", c_i32),
     ]
 
 

@@ -108,6 +108,22 @@ __device__ __forceinline__ T buffer_load8(__amdgpu_buffer_rsrc_t r, uint32_t byt
   return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
 }
 
+// V consecutive 8-byte elements (V = 1 or 2) from one bounds-checked buffer load.
+template <typename T, int V>
+__device__ __forceinline__ void buffer_load_vec(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, T* out) {
+  static_assert(sizeof(T) == 8 && (V == 1 || V == 2), "one or two 8-byte elements");
+  if constexpr (V == 1) {
+    out[0] = buffer_load8<T>(r, byte_off);
+  } else {
+    struct Pair {
+      T x, y;
+    };
+    const Pair p = __builtin_bit_cast(Pair, __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0));
+    out[0] = p.x;
+    out[1] = p.y;
+  }
+}
+
 }  // namespace tamm
 
 namespace tamm {
@@ -115,34 +131,51 @@ namespace tamm {
 // Per-thread gather state of one contraction workgroup (shared by the float64 and mixed kernels).
 //
 // A chunk of A is MT rows x KT summed indices, of B NT rows x KT.  With a k-contiguous operand
-// (its stride-1 label is summed) the lanes run along k: a thread owns one k and AE (BE) rows.
-// Otherwise the lanes run along the rows: element e of a thread is the flat position
-// tid + e*NTHR of the [k][row] chunk, so consecutive lanes read consecutive rows.  When the row
-// count divides the thread count a thread keeps one row and AE (BE) k positions; otherwise
-// (e.g. 80 rows, 256 threads) every element has its own row and k.
+// (its stride-1 label is summed) the lanes run along k: a thread owns one group of V
+// consecutive k and AE/V rows.  Otherwise the lanes run along the rows: load q of a thread is
+// the flat position tid + q*NTHR of the [k][row group] chunk (row groups of V consecutive rows),
+// so consecutive lanes read consecutive rows.  When the row-group count divides the thread count
+// a thread keeps one row group and AE/V k positions; otherwise (e.g. 80 rows, 256 threads) every
+// load has its own row and k.  V = 2 (16-byte loads) is used when the planner has checked that
+// every pair of table entries it groups is adjacent in memory.
 //
 // Everything is branch-free: rows, columns and k positions outside the block read the padding
 // entries of the offset tables (kTableInvalid), whose element offset is beyond the buffer
 // resource, and the buffer hardware returns zero for them.  Table entries are fetched a chunk
 // ahead of the data, so no dependent table->data chain sits in front of the MFMAs.
-template <int R, int KT, int NTHR, bool KC>
+template <int R, int KT, int NTHR, bool KC, int V>
 struct GatherMap {
   static constexpr int E = R * KT / NTHR;                       // elements per thread
-  static constexpr bool ROW_FIXED = !KC && (NTHR % R == 0);     // one row per thread
-  static constexpr int NR = KC ? E : (ROW_FIXED ? 1 : E);       // distinct row-table entries
-  static constexpr int NK = KC ? 1 : E;                         // distinct k-table entries
-  static_assert(R * KT % NTHR == 0, "chunk elements must split evenly over the threads");
-  static_assert(!KC || (NTHR % KT == 0 && R % (NTHR / KT) == 0), "k-contiguous gather mapping");
-  __device__ static int row(int tid, int e) { return KC ? tid / KT + e * (NTHR / KT) : (tid + e * NTHR) % R; }
-  __device__ static int k(int tid, int e) { return KC ? tid % KT : (tid + e * NTHR) / R; }
-  __device__ static int ridx(int e) { return KC ? e : (ROW_FIXED ? 0 : e); }  // row entry of element e
-  __device__ static int kidx(int e) { return KC ? 0 : e; }                    // k entry of element e
+  static constexpr int L = E / V;                               // loads per thread
+  static constexpr int KG = KT / V;                             // k groups per row (lanes along k)
+  static constexpr int RG = R / V;                              // row groups (lanes along rows)
+  static constexpr bool ROW_FIXED = !KC && (NTHR % RG == 0);    // one row group per thread
+  static constexpr int NR = KC ? L : (ROW_FIXED ? 1 : L);       // distinct row-table entries
+  static constexpr int NK = KC ? 1 : L;                         // distinct k-table entries
+  static_assert(R * KT % NTHR == 0 && E % V == 0 && R % V == 0 && KT % V == 0, "chunk must split evenly");
+  static_assert(KC || (RG * KT) % NTHR == 0, "row-group gather mapping");
+  static_assert(!KC || (NTHR % KG == 0 && R % (NTHR / KG) == 0), "k-contiguous gather mapping");
+  // row and k of element v of load q
+  __device__ static int row(int tid, int q, int v) {
+    return KC ? tid / KG + q * (NTHR / KG) : ((tid + q * NTHR) % RG) * V + v;
+  }
+  __device__ static int k(int tid, int q, int v) { return KC ? (tid % KG) * V + v : (tid + q * NTHR) / RG; }
+  __device__ static int ridx(int q) { return KC ? q : (ROW_FIXED ? 0 : q); }  // row entry of load q
+  __device__ static int kidx(int q) { return KC ? 0 : q; }                    // k entry of load q
 };
 
-template <int MT, int NT, int KT, int NTHR, bool A_KC, bool B_KC, typename T>
+// Whether a chunk of R rows x KT splits into 16-byte (two-element) loads under the mapping above.
+template <int R, int KT, int NTHR, bool KC>
+constexpr bool gather_pairs_fit() {
+  const int e = R * KT / NTHR;
+  if (R * KT % NTHR != 0 || e % 2 != 0 || R % 2 != 0 || KT % 2 != 0) return false;
+  return KC ? (NTHR % (KT / 2) == 0 && R % (NTHR / (KT / 2)) == 0) : ((R / 2) * KT % NTHR == 0);
+}
+
+template <int MT, int NT, int KT, int NTHR, bool A_KC, bool B_KC, typename T, int V = 1>
 struct Gather {
-  using MA = GatherMap<MT, KT, NTHR, A_KC>;
-  using MB = GatherMap<NT, KT, NTHR, B_KC>;
+  using MA = GatherMap<MT, KT, NTHR, A_KC, V>;
+  using MB = GatherMap<NT, KT, NTHR, B_KC, V>;
   static constexpr int AE = MA::E, BE = MB::E;
   static constexpr int A_NR = MA::NR, A_NK = MA::NK, B_NR = MB::NR, B_NK = MB::NK;
 
@@ -152,7 +185,7 @@ struct Gather {
   uint32_t a_bytes, b_bytes;
   int a_rt[A_NR], b_rt[B_NR];             // row table entries (elements; kTableInvalid past the block)
   int a_kt[A_NK], b_kt[B_NK];             // k table entries (elements; kTableInvalid past the block)
-  T ra[AE], rb[BE];
+  T ra[AE], rb[BE];                       // element q*V + v: element v of load q
 
   __device__ void init(int t) { tid = t; }
   __device__ void setup_pair(const PairDesc& d, const int32_t* pool, const T* A, const T* B, int m0, int n0, int mext,
@@ -162,31 +195,32 @@ struct Gather {
     a_bytes = (uint32_t)((int64_t)mext * d.kext * 8);
     b_bytes = (uint32_t)((int64_t)next * d.kext * 8);
 #pragma unroll
-    for (int e = 0; e < A_NR; ++e) a_rt[e] = gload(pool + d.a_tabM + m0 + MA::row(tid, e));
+    for (int q = 0; q < A_NR; ++q) a_rt[q] = gload(pool + d.a_tabM + m0 + MA::row(tid, q, 0));
 #pragma unroll
-    for (int e = 0; e < B_NR; ++e) b_rt[e] = gload(pool + d.b_tabN + n0 + MB::row(tid, e));
+    for (int q = 0; q < B_NR; ++q) b_rt[q] = gload(pool + d.b_tabN + n0 + MB::row(tid, q, 0));
   }
   __device__ void load_tables(const PairDesc& d, const int32_t* pool, int kbase) {
 #pragma unroll
-    for (int e = 0; e < A_NK; ++e) a_kt[e] = gload(pool + d.a_tabK + kbase + MA::k(tid, e));
+    for (int q = 0; q < A_NK; ++q) a_kt[q] = gload(pool + d.a_tabK + kbase + MA::k(tid, q, 0));
 #pragma unroll
-    for (int e = 0; e < B_NK; ++e) b_kt[e] = gload(pool + d.b_tabK + kbase + MB::k(tid, e));
+    for (int q = 0; q < B_NK; ++q) b_kt[q] = gload(pool + d.b_tabK + kbase + MB::k(tid, q, 0));
   }
   __device__ void load_data() {
     // resources built here from wave-uniform values, so that they live in scalar registers
     const __amdgpu_buffer_rsrc_t a_rsrc = block_rsrc(a_base, a_bytes);
     const __amdgpu_buffer_rsrc_t b_rsrc = block_rsrc(b_base, b_bytes);
 #pragma unroll
-    for (int e = 0; e < AE; ++e) ra[e] = buffer_load8<T>(a_rsrc, (uint32_t)(a_rt[MA::ridx(e)] + a_kt[MA::kidx(e)]) * 8u);
+    for (int q = 0; q < MA::L; ++q)
+      buffer_load_vec<T, V>(a_rsrc, (uint32_t)(a_rt[MA::ridx(q)] + a_kt[MA::kidx(q)]) * 8u, ra + q * V);
 #pragma unroll
-    for (int e = 0; e < BE; ++e) rb[e] = buffer_load8<T>(b_rsrc, (uint32_t)(b_rt[MB::ridx(e)] + b_kt[MB::kidx(e)]) * 8u);
+    for (int q = 0; q < MB::L; ++q)
+      buffer_load_vec<T, V>(b_rsrc, (uint32_t)(b_rt[MB::ridx(q)] + b_kt[MB::kidx(q)]) * 8u, rb + q * V);
   }
-  __device__ int a_lds_row(int e) const { return MA::row(tid, e); }
-  __device__ int a_lds_k(int e) const { return MA::k(tid, e); }
-  __device__ int b_lds_row(int e) const { return MB::row(tid, e); }
-  __device__ int b_lds_k(int e) const { return MB::k(tid, e); }
+  __device__ int a_lds_row(int e) const { return MA::row(tid, e / V, e % V); }
+  __device__ int a_lds_k(int e) const { return MA::k(tid, e / V, e % V); }
+  __device__ int b_lds_row(int e) const { return MB::row(tid, e / V, e % V); }
+  __device__ int b_lds_k(int e) const { return MB::k(tid, e / V, e % V); }
 };
-
 
 // Chunk pipeline of one work item, shared by the contraction kernels.  LDS holds two chunk
 // buffers and there is one barrier per chunk: while compute(buf, ...) runs the MFMAs of chunk c
@@ -208,7 +242,7 @@ __device__ __forceinline__ void chunk_pipeline(G& g, const PairDesc* pairs, int 
   int nf = 0;
   auto push = [&]() {
     const int kend = k1 + KT;
-    const bool f = kend >= d1.kext || (W > 0 && kend % W == 0);
+    const bool f = kend >= d1.kext || (W > 0 && kend % (W > 0 ? W : 1) == 0);
     fifo |= (f ? 1u : 0u) << nf;
     ++nf;
   };

@@ -101,7 +101,7 @@ hipError_t launch_screen(const ScreenParams& p, hipStream_t s) {
 // from a counter (the grouped launch); the item order is the plan's.  The operands' gather
 // layouts (A_KC, B_KC) are template parameters: "layout" = 2*A_KC + B_KC.
 // ---------------------------------------------------------------------------------------------
-template <int MT, int NT, int KT, int WGM, int WGN, int OCC, bool A_KC, bool B_KC>
+template <int MT, int NT, int KT, int WGM, int WGN, int OCC, bool A_KC, bool B_KC, int VEC>
 __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(OCC))) void k_contract_f64(ContractParams P) {
   constexpr int NTHR = 64 * WGM * WGN;
   constexpr int WM = MT / WGM, WN = NT / WGN;
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
   constexpr int NS = KT / 4;  // MFMA k-steps per chunk
   static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile must be a multiple of 16");
   static_assert(KT % 4 == 0 && NS >= 2, "KT a multiple of 4, at least 8");
-  using G = Gather<MT, NT, KT, NTHR, A_KC, B_KC, double>;
+  using G = Gather<MT, NT, KT, NTHR, A_KC, B_KC, double, VEC>;
   __shared__ double As[2][MT * LD];
   __shared__ double Bs[2][NT * LD];
   __shared__ int s_next;
@@ -286,29 +286,39 @@ static const F64Config kF64Configs[] = {TAMM_F64_CONFIGS(TAMM_CFG_ENTRY)};
 int f64_config_count() { return (int)(sizeof(kF64Configs) / sizeof(kF64Configs[0])); }
 const F64Config& f64_config(int id) { return kF64Configs[id]; }
 
+// Gather layout index: bit 1 = A k-contiguous, bit 0 = B k-contiguous, bit 2 = 16-byte gathers.
+// A tile shape whose chunks do not split into pairs runs the 8-byte gather for bit 2 as well.
+template <int MT, int NT, int KT, int WGM, int WGN, int OCC, int LAYOUT>
+static constexpr auto contract_kernel() {
+  constexpr bool akc = (LAYOUT & 2) != 0, bkc = (LAYOUT & 1) != 0;
+  constexpr int nthr = 64 * WGM * WGN;
+  constexpr bool pairs = (LAYOUT & 4) != 0 && gather_pairs_fit<MT, KT, nthr, akc>() && gather_pairs_fit<NT, KT, nthr, bkc>();
+  return k_contract_f64<MT, NT, KT, WGM, WGN, OCC, akc, bkc, pairs ? 2 : 1>;
+}
+
+template <int MT, int NT, int KT, int WGM, int WGN, int OCC>
+static auto contract_kernel_for(int layout) {
+  using K = decltype(contract_kernel<MT, NT, KT, WGM, WGN, OCC, 0>());
+  static const K table[8] = {contract_kernel<MT, NT, KT, WGM, WGN, OCC, 0>(), contract_kernel<MT, NT, KT, WGM, WGN, OCC, 1>(),
+                             contract_kernel<MT, NT, KT, WGM, WGN, OCC, 2>(), contract_kernel<MT, NT, KT, WGM, WGN, OCC, 3>(),
+                             contract_kernel<MT, NT, KT, WGM, WGN, OCC, 4>(), contract_kernel<MT, NT, KT, WGM, WGN, OCC, 5>(),
+                             contract_kernel<MT, NT, KT, WGM, WGN, OCC, 6>(), contract_kernel<MT, NT, KT, WGM, WGN, OCC, 7>()};
+  return table[layout & 7];
+}
+
 template <int MT, int NT, int KT, int WGM, int WGN, int OCC>
 static hipError_t launch_cfg(int layout, const ContractParams& p, int grid, hipStream_t s) {
   const dim3 g(grid > 0 ? grid : p.n_work), b(64 * WGM * WGN);
-  switch (layout) {
-    case 3: hipLaunchKernelGGL((k_contract_f64<MT, NT, KT, WGM, WGN, OCC, true, true>), g, b, 0, s, p); break;
-    case 2: hipLaunchKernelGGL((k_contract_f64<MT, NT, KT, WGM, WGN, OCC, true, false>), g, b, 0, s, p); break;
-    case 1: hipLaunchKernelGGL((k_contract_f64<MT, NT, KT, WGM, WGN, OCC, false, true>), g, b, 0, s, p); break;
-    default: hipLaunchKernelGGL((k_contract_f64<MT, NT, KT, WGM, WGN, OCC, false, false>), g, b, 0, s, p); break;
-  }
+  const auto kernel = contract_kernel_for<MT, NT, KT, WGM, WGN, OCC>(layout);
+  hipLaunchKernelGGL(kernel, g, b, 0, s, p);
   return hipGetLastError();
 }
 
 template <int MT, int NT, int KT, int WGM, int WGN, int OCC>
 static int occupancy_cfg(int layout) {
   int n = 0;
-  const int threads = 64 * WGM * WGN;
-  hipError_t e;
-  switch (layout) {
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, OCC, true, true>, threads, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, OCC, true, false>, threads, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, OCC, false, true>, threads, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_contract_f64<MT, NT, KT, WGM, WGN, OCC, false, false>, threads, 0); break;
-  }
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &n, contract_kernel_for<MT, NT, KT, WGM, WGN, OCC>(layout), 64 * WGM * WGN, 0);
   return e == hipSuccess && n > 0 ? n : 1;
 }
 

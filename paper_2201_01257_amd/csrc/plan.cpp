@@ -40,6 +40,14 @@ static int32_t pool_push_table(std::vector<int32_t>& pool, const std::vector<int
   return start;
 }
 
+// True when entries 2j and 2j+1 of a table are adjacent elements for every j (even length).
+static bool pairs_adjacent(const std::vector<int64_t>& t) {
+  if (t.size() % 2) return false;
+  for (size_t j = 0; j + 1 < t.size(); j += 2)
+    if (t[j + 1] != t[j] + 1) return false;
+  return true;
+}
+
 // Offset table of one label group inside blocks of one operand shape: flattened index (mixed
 // radix over `group`, last fastest) -> element offset in the row-major block.
 std::vector<int64_t> group_table(const std::vector<int>& group, const std::vector<int64_t>& lab_ext,
@@ -87,6 +95,7 @@ struct tamm_plan {
   std::vector<int> M, N, K;        // label indices in flattening order (last fastest)
   std::vector<int> k_lhs_order;    // for each K label in lhs order: its position in K
   bool a_kc = true, b_kc = true;
+  bool pairs = false;              // every gathered pair of table entries is adjacent (16-byte loads)
   std::vector<int32_t> pool;
   ScreenDesc sd{};                 // device pointers filled when bound
   int64_t n_kt = 1;
@@ -113,6 +122,11 @@ struct tamm_plan {
 };
 
 static int configure_work(tamm_plan* p, int config, int k_splits);
+
+// Gather layout index of a plan's kernels: bit 1 = A k-contiguous, bit 0 = B k-contiguous,
+// bit 2 = 16-byte (two-element) gathers.
+static int gather_layout(const tamm_plan* p) { return 2 * (p->a_kc ? 1 : 0) + (p->b_kc ? 1 : 0) + (p->pairs ? 4 : 0); }
+constexpr int kLayouts = 8;
 
 static Layout make_layout(const tamm_plan* p, size_t base) {
   Layout L;
@@ -287,9 +301,10 @@ extern "C" int tamm_plan_create(tamm_tensor* out, const char* out_lbl, const tam
   OpInfo ai = op_info(p->A, a_dim_label), bi = op_info(p->B, b_dim_label), oi = op_info(out, o_dim_label);
   if (ai.ncls + bi.ncls + oi.ncls > 100000) return fail(TAMM_ERR_UNSUPPORTED, "too many distinct block shapes");
   auto build_tables = [&](const OpInfo& o, const std::vector<int>& g1, const std::vector<int>& g2,
-                          std::vector<int64_t>& start1, std::vector<int64_t>& start2) {
+                          std::vector<int64_t>& start1, std::vector<int64_t>& start2, bool& pairs1, bool& pairs2) {
     start1.assign(o.ncls, 0);
     start2.assign(o.ncls, 0);
+    pairs1 = pairs2 = true;
     std::vector<int64_t> lab_ext(nl, 1), lab_stride(nl, 0);
     for (int64_t c = 0; c < o.ncls; ++c) {
       int64_t stride = 1;
@@ -301,8 +316,11 @@ extern "C" int tamm_plan_create(tamm_tensor* out, const char* out_lbl, const tam
         stride *= L.cls_size[cl];
       }
       if (stride > INT32_MAX) return false;
-      start1[c] = pool_push_table(pool, group_table(g1, lab_ext, lab_stride));
-      start2[c] = pool_push_table(pool, group_table(g2, lab_ext, lab_stride));
+      const std::vector<int64_t> t1 = group_table(g1, lab_ext, lab_stride), t2 = group_table(g2, lab_ext, lab_stride);
+      pairs1 = pairs1 && pairs_adjacent(t1);
+      pairs2 = pairs2 && pairs_adjacent(t2);
+      start1[c] = pool_push_table(pool, t1);
+      start2[c] = pool_push_table(pool, t2);
       if (pool.size() > (size_t)INT32_MAX / 2) return false;
     }
     return true;
@@ -310,8 +328,12 @@ extern "C" int tamm_plan_create(tamm_tensor* out, const char* out_lbl, const tam
   if (p->A->max_block >= kTableInvalid || p->B->max_block >= kTableInvalid)
     return fail(TAMM_ERR_UNSUPPORTED, "operand blocks of 2^27 or more elements are not supported");
   std::vector<int64_t> aM, aK, bK, bN, oM, oN;
-  if (!build_tables(ai, p->M, p->K, aM, aK) || !build_tables(bi, p->K, p->N, bK, bN) || !build_tables(oi, p->M, p->N, oM, oN))
+  bool aM_pairs, aK_pairs, bK_pairs, bN_pairs, oM_pairs, oN_pairs;
+  if (!build_tables(ai, p->M, p->K, aM, aK, aM_pairs, aK_pairs) || !build_tables(bi, p->K, p->N, bK, bN, bK_pairs, bN_pairs) ||
+      !build_tables(oi, p->M, p->N, oM, oN, oM_pairs, oN_pairs))
     return fail(TAMM_ERR_UNSUPPORTED, "a block has more than 2^31 elements or the offset tables are too large");
+  // 16-byte gathers pair consecutive k of a k-contiguous operand, consecutive rows otherwise
+  p->pairs = (p->a_kc ? aK_pairs : aM_pairs) && (p->b_kc ? bK_pairs : bN_pairs);
   if (precision == TAMM_PREC_BF16X3 || precision == TAMM_PREC_BF16X4_ALIGNED) {
     // split work per stored operand block: rows (M for A, N for B) x K windows
     auto prep_list = [&](const OpInfo& o, const std::vector<int64_t>& rowtab, const std::vector<int64_t>& ktab,
@@ -606,6 +628,7 @@ static int configure_work(tamm_plan* p, int config, int k_splits) {
   p->stats.work_items = (int64_t)p->work.size();
   p->stats.kernel_config = config;
   p->stats.k_splits = k_splits;
+  p->stats.gather_layout = gather_layout(p);
   p->lay = make_layout(p, 0);
   size_t off = p->lay.end;
   p->off_work = off;
@@ -730,7 +753,7 @@ static int contract_launch(tamm_plan* p, double alpha, double beta, hipStream_t 
   cp.work = (const WorkItem*)(p->ws + p->off_work);
   cp.next_item = nullptr;
   cp.n_work = (int32_t)p->work.size();
-  const int layout = 2 * (p->a_kc ? 1 : 0) + (p->b_kc ? 1 : 0);
+  const int layout = gather_layout(p);
   if (p->prec == TAMM_PREC_F64) {
     HIP_TRY(launch_contract_f64(p->config, layout, cp, 0, s));
   } else {
@@ -755,7 +778,7 @@ static int contract_launch(tamm_plan* p, double alpha, double beta, hipStream_t 
       cp.single.A = (const double*)(p->ws + p->off_xA);
       cp.single.B = (const double*)(p->ws + p->off_xB);
     }
-    HIP_TRY(launch_contract_mixed(p->prec, p->config, layout, cp, s));
+    HIP_TRY(launch_contract_mixed(p->prec, p->config, layout & 3, cp, s));
   }
   if (p->k_splits > 1) {
     const TileCfg f = cfg_get(p->prec, p->config);
@@ -925,7 +948,7 @@ struct tamm_group {
   size_t off_sdesc = 0, off_pdesc = 0, off_sitems = 0, off_work = 0, off_counter = 0, ws_size = 0;
   std::vector<int32_t> sitem_prob, sitem_block;
   std::vector<WorkItem> work;       // grouped by gather layout class, each class longest first
-  int32_t cls_begin[5] = {0, 0, 0, 0, 0};  // work range of layout class c: [cls_begin[c], cls_begin[c+1])
+  int32_t cls_begin[kLayouts + 1] = {};  // work range of gather layout c: [cls_begin[c], cls_begin[c+1])
   int config = -1;
   int grid = 0;   // 0: automatic
   uint64_t signature = 0;
@@ -985,14 +1008,12 @@ static int group_configure(tamm_group* g, int config) {
   }
   std::stable_sort(tiles.begin(), tiles.end(), [](const Tile& x, const Tile& y) { return x.cost > y.cost; });
   g->work.clear();
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < kLayouts; ++c) {
     g->cls_begin[c] = (int32_t)g->work.size();
-    for (auto& t : tiles) {
-      const tamm_plan* p = g->plans[t.w.prob];
-      if (2 * (p->a_kc ? 1 : 0) + (p->b_kc ? 1 : 0) == c) g->work.push_back(t.w);
-    }
+    for (auto& t : tiles)
+      if (gather_layout(g->plans[t.w.prob]) == c) g->work.push_back(t.w);
   }
-  g->cls_begin[4] = (int32_t)g->work.size();
+  g->cls_begin[kLayouts] = (int32_t)g->work.size();
   g->config = config;
   size_t off = 0;
   g->lays.clear();
@@ -1008,8 +1029,8 @@ static int group_configure(tamm_group* g, int config) {
   off = align256(off + g->sitem_prob.size() * 2 * sizeof(int32_t));
   g->off_work = off;
   off = align256(off + g->work.size() * sizeof(WorkItem));
-  g->off_counter = off;  // one work counter per layout class
-  off = align256(off + 4 * sizeof(int32_t));
+  g->off_counter = off;  // one work counter per gather layout
+  off = align256(off + kLayouts * sizeof(int32_t));
   g->ws_size = off;
   g->bound = false;
   group_drop_graph(g);
@@ -1107,8 +1128,8 @@ static int group_enqueue(tamm_group* g, hipStream_t s) {
   sp.item_block = sp.item_prob + g->sitem_prob.size();
   sp.n_items = (int32_t)g->sitem_prob.size();
   HIP_TRY(launch_screen(sp, s));
-  // one persistent launch per operand-layout class present in the group
-  for (int c = 0; c < 4; ++c) {
+  // one persistent launch per gather layout present in the group
+  for (int c = 0; c < kLayouts; ++c) {
     const int n = g->cls_begin[c + 1] - g->cls_begin[c];
     if (n <= 0) continue;
     const int grid = group_grid(g, c, n);

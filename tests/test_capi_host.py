@@ -159,3 +159,31 @@ def test_every_kernel_config_plans():
             assert st["work_items"] % ks == 0
             assert p.workspace_size() > 0
             assert p.config_name().startswith("f64_")
+
+
+def test_operand_blocks_beyond_the_gather_range_are_rejected():
+    # one 512^3 block (2^27 elements, 1 GiB): the gathers address operand blocks below 2^27 elements
+    big = tm.Space.fixed(512, 512)
+    small = tm.Space.fixed(4, 4)
+    dense = lambda t, s: True  # noqa: E731
+    A = tm.Tensor([big, big, big], nonzero=dense, device=None)
+    B = tm.Tensor([big, small], nonzero=dense, device=None)
+    C = tm.Tensor([big, big, small], nonzero=dense, device=None)
+    assert status_of(lambda: tm.Plan(C, "abj", A, "abk", B, "kj", bind=False)) == "TAMM_ERR_UNSUPPORTED"
+    # one tile smaller and the same contraction plans
+    ok = tm.Space.fixed(500, 500)
+    A2 = tm.Tensor([ok, ok, ok], nonzero=dense, device=None)
+    B2 = tm.Tensor([ok, small], nonzero=dense, device=None)
+    C2 = tm.Tensor([ok, ok, small], nonzero=dense, device=None)
+    tm.Plan(C2, "abj", A2, "abk", B2, "kj", bind=False)
+
+
+def test_gather_layout_pairs_only_for_adjacent_table_pairs():
+    # even tile sizes: every grouped pair of table entries is adjacent -> 16-byte gathers
+    even = term_structures("ladder", (12, 12, 12), (16, 24, 16), None)[0]
+    st = tm.Plan(*even, bind=False).stats()
+    assert st["gather_layout"] & 4
+    assert st["gather_layout"] & 3 == 2  # V[abcd]: A gathered along k; T[cdij]: B along rows
+    # an odd tile size on the stride-1 labels -> 8-byte gathers
+    odd = term_structures("ladder", (11, 11, 11), (15, 4, 15), None)[0]
+    assert not tm.Plan(*odd, bind=False).stats()["gather_layout"] & 4

@@ -51,6 +51,8 @@ def test_config0_ladder_full():
 
 
 SMALL = (24, 40, 12, 16)  # O=24 -> [12a,12b]; V=40 -> [16,4,16,4]: several macro-tiles and ragged tails
+ODD = (22, 38, 11, 15)    # odd tile sizes: the gathers cannot pair table entries (8-byte loads)
+N_CONFIGS = 15            # float64 kernel configurations (checked against the library below)
 
 
 @pytest.mark.parametrize("term", list(TERMS))
@@ -61,12 +63,15 @@ def test_terms_small_ragged(term):
     assert rel <= TOL, (term, rel, mx)
 
 
+@pytest.mark.parametrize("shape", [SMALL, ODD], ids=["pairs", "single"])
 @pytest.mark.parametrize("term", ["ladder", "ring", "t1_o", "hh"])
-@pytest.mark.parametrize("config", range(5))
+@pytest.mark.parametrize("config", range(N_CONFIGS))
 @pytest.mark.parametrize("k_splits", [1, 3])
-def test_every_config_and_split(term, config, k_splits):
-    prob = Problem(*SMALL)
+def test_every_config_and_split(term, config, k_splits, shape):
+    prob = Problem(*shape)
     O, plan, ref = run_term(prob, term, alpha=-0.7, beta=0.3, config=config, k_splits=k_splits)
+    assert plan.config_count() == N_CONFIGS
+    assert bool(plan.stats()["gather_layout"] & 4) == (shape == SMALL)
     rel, mx = max_rel(O.to_blocks(), ref.blocks)
     assert rel <= TOL, (term, config, k_splits, rel, mx)
 
