@@ -219,7 +219,9 @@ def main():
         ms = acc[t] / args.steps
         per_term[t] = {"ms": round(ms, 4), "useful_gflop": round(flops[t] / 1e9, 3),
                        "tflops": round(flops[t] / (ms * 1e-3) / 1e12, 3),
-                       "config": plans[t].config_name(), "k_splits": plans[t].stats()["k_splits"]}
+                       "config": plans[t].config_name(), "k_splits": plans[t].stats()["k_splits"],
+                       "work_items": plans[t].stats()["work_items"],
+                       "algorithmic_bytes": plans[t].stats()["algorithmic_bytes"]}
     lad_ms = acc["ladder_kernel"] / args.steps
     achieved = flops["ladder"] / (lad_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64_MFMA_TFLOPS, "unit": "TFLOP/s",
@@ -485,6 +487,9 @@ def run_mixed(args):
     results = {}
     for prec in precisions:
         plans = {t: tm.Plan(R, "abij", L, ll, Rr, rl, precision=prec) for t, (L, ll, Rr, rl, a) in terms.items()}
+        if not args.no_tune:
+            for t, p in plans.items():  # the library's autotuner, outside the timed region
+                p.autotune(args.tune_cache, reps=2)
         errs = {}
         for t, p in plans.items():
             p.execute(terms[t][4], 0.0)

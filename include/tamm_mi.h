@@ -181,7 +181,10 @@ typedef struct {
                              bit 1: A's stride-1 label is summed (lanes gather along k);
                              bit 0: the same for B; bit 2: every pair of offset-table entries
                              the gathers group is adjacent in memory, so the float64 kernels
-                             load two elements per lane (16-byte loads)                        */
+                             load two elements per lane (16-byte loads); bit 3: split-bfloat16
+                             precisions store the split operands as slice planes, each block
+                             [row][k], because every operand block's K extent is a multiple
+                             of 8 (16-byte gathers of 8 slices)                              */
   int32_t reserved;       /* zero                                                              */
 } tamm_plan_stats;
 

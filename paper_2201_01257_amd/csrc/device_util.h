@@ -74,6 +74,8 @@ __device__ __forceinline__ ProblemDesc wave_uniform(const ProblemDesc& d) {
   u.a_kc = wave_uniform(d.a_kc);
   u.b_kc = wave_uniform(d.b_kc);
   u.pad = 0;
+  u.a_plane = wave_uniform(d.a_plane);
+  u.b_plane = wave_uniform(d.b_plane);
   return u;
 }
 __device__ __forceinline__ WorkItem wave_uniform(const WorkItem& w) {

@@ -74,8 +74,10 @@ struct ProblemDesc {
   int32_t a_kc;      // 1: A's stride-1 label is summed (gather lanes run along k), 0: along m
   int32_t b_kc;      // 1: B's stride-1 label is summed, 0: along n
   int32_t pad;
+  int64_t a_plane;   // split-bfloat16 planes: elements between the slice planes of A (else 0)
+  int64_t b_plane;   // the same for B
 };
-static_assert(sizeof(ProblemDesc) == 96, "ProblemDesc layout");
+static_assert(sizeof(ProblemDesc) == 112, "ProblemDesc layout");
 
 struct ContractParams {
   ProblemDesc single;         // used when probs is null (one plan)

@@ -19,6 +19,8 @@
 //           its own accumulator, and only the small residual products see float32 rounding.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_util.h"
 #include "internal.h"
 #include "mixed.h"
@@ -28,6 +30,7 @@ namespace tamm {
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------------------------
 // operand split
@@ -107,6 +110,63 @@ __global__ __launch_bounds__(256) void k_prep_split(PrepParams P) {
   const int k0 = win * kSplitWindow;
   const int k1 = min(pb.kext, k0 + kSplitWindow);
   const int32_t* __restrict__ pool = P.pool;
+  if (P.planes) {
+    // planes layout (every K extent a multiple of 8): a lane converts 4 (lanes along k) or 8
+    // (lanes along rows) consecutive k of one row and writes each slice plane's part at once
+    const int ns = P.aligned ? 4 : 3;
+    unsigned short* __restrict__ out = static_cast<unsigned short*>(P.out);
+    if (!ROWS_ALONG_LANES) {
+      const int row = rg;
+      const int64_t rowoff = pb.off + pool[pb.tab_row + row];
+      static_assert(kSplitWindow == 4 * 64, "a wave converts one window, 4 k per lane");
+      const int k = k0 + 4 * lane;
+      double x[4];
+      double mx = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        x[i] = (k < k1) ? P.x[rowoff + pool[pb.tab_k + k + i]] : 0.0;
+        mx = fmax(mx, fabs(x[i]));
+      }
+      const double scale = window_scale(wave_max(mx));
+      if (k < k1) {
+        uint64_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = P.aligned ? split_aligned(x[i], scale) : split_plain(x[i]);
+        const int64_t pos = pb.off + (int64_t)row * pb.kext + k;
+        for (int sl = 0; sl < ns; ++sl) {
+          uint64_t v = 0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v |= ((w[i] >> (16 * sl)) & 0xFFFFull) << (16 * i);
+          *reinterpret_cast<uint64_t*>(out + sl * P.plane_stride + pos) = v;
+        }
+      }
+    } else {
+      const int row = rg * 64 + lane;
+      if (row >= pb.rows) return;
+      const int64_t rowoff = pb.off + pool[pb.tab_row + row];
+      double mx = 0.0;
+      if (P.aligned)
+        for (int k = k0; k < k1; ++k) mx = fmax(mx, fabs(P.x[rowoff + pool[pb.tab_k + k]]));
+      const double scale = window_scale(mx);
+      for (int k = k0; k < k1; k += 8) {
+        uint64_t w[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const double v = P.x[rowoff + pool[pb.tab_k + k + i]];
+          w[i] = P.aligned ? split_aligned(v, scale) : split_plain(v);
+        }
+        const int64_t pos = pb.off + (int64_t)row * pb.kext + k;
+        for (int sl = 0; sl < ns; ++sl) {
+          u4_t v;
+#pragma unroll
+          for (int h = 0; h < 4; ++h)
+            v[h] = (uint32_t)((w[2 * h] >> (16 * sl)) & 0xFFFFu) | ((uint32_t)((w[2 * h + 1] >> (16 * sl)) & 0xFFFFu) << 16);
+          *reinterpret_cast<u4_t*>(out + sl * P.plane_stride + pos) = v;
+        }
+      }
+    }
+    return;
+  }
   if (!ROWS_ALONG_LANES) {
     const int row = rg;
     const int64_t rowoff = pb.off + pool[pb.tab_row + row];
@@ -122,7 +182,8 @@ __global__ __launch_bounds__(256) void k_prep_split(PrepParams P) {
 #pragma unroll
     for (int j = 0; j < kSplitWindow / 64; ++j) {
       const int k = k0 + lane + 64 * j;
-      if (k < k1) P.out[rowoff + pool[pb.tab_k + k]] = P.aligned ? split_aligned(x[j], scale) : split_plain(x[j]);
+      if (k < k1)
+        static_cast<uint64_t*>(P.out)[rowoff + pool[pb.tab_k + k]] = P.aligned ? split_aligned(x[j], scale) : split_plain(x[j]);
     }
   } else {
     const int row = rg * 64 + lane;
@@ -135,7 +196,7 @@ __global__ __launch_bounds__(256) void k_prep_split(PrepParams P) {
     for (int k = k0; k < k1; ++k) {
       const int64_t a = rowoff + pool[pb.tab_k + k];
       const double v = P.x[a];
-      P.out[a] = P.aligned ? split_aligned(v, scale) : split_plain(v);
+      static_cast<uint64_t*>(P.out)[a] = P.aligned ? split_aligned(v, scale) : split_plain(v);
     }
   }
 }
@@ -273,24 +334,108 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
 }
 
 // ---------------------------------------------------------------------------------------------
+// Gather of split operands in the planes layout: plane s holds bfloat16 slice s of every element,
+// each block as [row][k] (flattened M or N rows, flattened K, k fastest) at the block's element
+// offset.  A lane moves 8 consecutive k of one row and plane with one 16-byte load and one
+// 16-byte LDS store.  The planner uses this layout only when every operand block's K extent is a
+// multiple of 8, so a group of 8 is either inside the block or wholly past its K extent; groups
+// past the rows or the K extent read zeros (offset beyond the buffer resource).
+// Same interface as Gather, for chunk_pipeline.
+// ---------------------------------------------------------------------------------------------
+// 16-byte unit permutation of LDS row r in the planes layout (rows of four 16-byte units).
+__device__ __forceinline__ int lds_swizzle(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+template <int MT, int NT, int KT, int NTHR, int NS>
+struct PlaneGather {
+  static constexpr int KG = KT / 8;           // 16-byte groups per row of a chunk
+  static constexpr int AJ = MT * KG / NTHR;   // loads per plane and thread
+  static constexpr int BJ = NT * KG / NTHR;
+  static_assert(KT % 8 == 0 && MT * KG % NTHR == 0 && NT * KG % NTHR == 0, "plane gather mapping");
+  static constexpr uint32_t kPast = 0x80000000u;  // byte offset beyond every block
+
+  int tid;
+  int64_t a_plane, b_plane;
+  const __bf16* a_base;
+  const __bf16* b_base;
+  int m0, n0, mext, next, kext, kbase;
+  u4_t ra[NS][AJ], rb[NS][BJ];
+
+  __device__ void init(int t, int64_t ap, int64_t bp) {
+    tid = t;
+    a_plane = ap;
+    b_plane = bp;
+  }
+  __device__ void setup_pair(const PairDesc& d, const int32_t*, const __bf16* A, const __bf16* B, int m0_, int n0_,
+                             int mext_, int next_) {
+    a_base = A + d.a_off;
+    b_base = B + d.b_off;
+    m0 = m0_;
+    n0 = n0_;
+    mext = mext_;
+    next = next_;
+    kext = d.kext;
+  }
+  __device__ void load_tables(const PairDesc&, const int32_t*, int kb) { kbase = kb; }
+  __device__ void load_data() {
+    const uint32_t a_bytes = (uint32_t)mext * (uint32_t)kext * 2u, b_bytes = (uint32_t)next * (uint32_t)kext * 2u;
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      const __amdgpu_buffer_rsrc_t ar = block_rsrc(a_base + sl * a_plane, a_bytes);
+      const __amdgpu_buffer_rsrc_t br = block_rsrc(b_base + sl * b_plane, b_bytes);
+#pragma unroll
+      for (int j = 0; j < AJ; ++j) {
+        const int p = tid + j * NTHR, r = m0 + p / KG, k = kbase + 8 * (p % KG);
+        const uint32_t off = (r < mext && k < kext) ? (uint32_t)(r * kext + k) * 2u : kPast;
+        ra[sl][j] = __builtin_bit_cast(u4_t, __builtin_amdgcn_raw_buffer_load_b128(ar, (int)off, 0, 0));
+      }
+#pragma unroll
+      for (int j = 0; j < BJ; ++j) {
+        const int p = tid + j * NTHR, r = n0 + p / KG, k = kbase + 8 * (p % KG);
+        const uint32_t off = (r < next && k < kext) ? (uint32_t)(r * kext + k) * 2u : kPast;
+        rb[sl][j] = __builtin_bit_cast(u4_t, __builtin_amdgcn_raw_buffer_load_b128(br, (int)off, 0, 0));
+      }
+    }
+  }
+  // LDS position (row, first k) of load j
+  __device__ int lds_row(int j) const { return (tid + j * NTHR) / KG; }
+  __device__ int lds_k(int j) const { return 8 * ((tid + j * NTHR) % KG); }
+};
+
+// ---------------------------------------------------------------------------------------------
 // split bfloat16 products (v_mfma_f32_16x16x32_bf16).  LDS holds NS slice planes per operand as
 // [row][k] bfloat16 with a row stride of KT+8 elements (an odd number of 16-byte units, so the
 // 16-byte fragment reads of 16 consecutive rows hit distinct banks).
 // ---------------------------------------------------------------------------------------------
-template <int MT, int NT, int KT, int WGM, int WGN, bool ALIGNED, bool A_KC, bool B_KC>
+template <int MT, int NT, int KT, int WGM, int WGN, bool ALIGNED, bool A_KC, bool B_KC, bool PLANES>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParams P) {
   constexpr int NTHR = 64 * WGM * WGN;
   constexpr int WM = MT / WGM, WN = NT / WGN, FM = WM / 16, FN = WN / 16;
   constexpr int NS = ALIGNED ? 4 : 3;
-  constexpr int LD = KT + 8;
+  // LDS rows of KT bfloat16.  Packed layout: padded to an odd number of 16-byte units.  Planes
+  // layout: unpadded, the 16-byte unit u of row r stored at unit u ^ lds_swizzle(r), which keeps
+  // the 16-byte stores (4 rows x 4 units per 16 lanes) and the MFMA operand reads (16 rows, one
+  // unit) free of bank conflicts for 32 or 64 banks.
+  constexpr int LD = PLANES ? KT : KT + 8;
   static_assert(KT % 32 == 0 && kSplitWindow % KT == 0, "chunks of whole MFMA k-steps tile the window");
-  static_assert(((LD * 2) / 16) % 2 == 1, "row stride must be an odd number of 16-byte units");
-  using G = Gather<MT, NT, KT, NTHR, A_KC, B_KC, uint64_t>;
+  static_assert(PLANES ? KT == 32 : ((LD * 2) / 16) % 2 == 1, "LDS row layout");
+  using G = std::conditional_t<PLANES, PlaneGather<MT, NT, KT, NTHR, NS>, Gather<MT, NT, KT, NTHR, A_KC, B_KC, uint64_t>>;
+  using E = std::conditional_t<PLANES, __bf16, uint64_t>;  // element type of the split operands
   __shared__ __attribute__((aligned(16))) __bf16 As[2][NS * MT * LD];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[2][NS * NT * LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM, lr = lane & 15, lq = lane >> 4;
-  const int a_frag = (wm * WM + lr) * LD + 8 * lq, b_frag = (wn * WN + lr) * LD + 8 * lq;
+  // operand read offsets of this lane (row block i / j, MFMA k-step 0)
+  int a_frag[FM], b_frag[FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const int r = wm * WM + i * 16 + lr;
+    a_frag[i] = r * LD + 8 * (PLANES ? (lq ^ lds_swizzle(r)) : lq);
+  }
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int r = wn * WN + j * 16 + lr;
+    b_frag[j] = r * LD + 8 * (PLANES ? (lq ^ lds_swizzle(r)) : lq);
+  }
   const int item = blockIdx.x;
   if (item >= P.n_work) return;
   const WorkItem w = wave_uniform(sload(P.work + item));
@@ -298,8 +443,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
   const OutBlockDesc blk = wave_uniform(sload(pr.blocks + w.ob));
   const int32_t* __restrict__ pool = pr.pool;
   const PairDesc* __restrict__ pairs = pr.pairs + blk.pair_base;
-  const uint64_t* Ap = reinterpret_cast<const uint64_t*>(pr.A);
-  const uint64_t* Bp = reinterpret_cast<const uint64_t*>(pr.B);
+  const E* Ap = reinterpret_cast<const E*>(pr.A);
+  const E* Bp = reinterpret_cast<const E*>(pr.B);
   const int cnt = wave_uniform(gload(pr.counts + w.ob));
   int pb = 0, pe = cnt;
   if (pr.k_splits > 1) {
@@ -307,7 +452,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
     pe = (int)(((int64_t)cnt * (w.split + 1)) / pr.k_splits);
   }
   G g;
-  g.init(tid);
+  if constexpr (PLANES) g.init(tid, pr.a_plane, pr.b_plane);
+  else g.init(tid);
   d4_t acc[FM][FN];
   f4_t lead[FM][FN], rest[FM][FN];
 #pragma unroll
@@ -320,19 +466,35 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
     }
   if (pb < pe) {
     auto store = [&](int b) {
-      unsigned short* As16 = reinterpret_cast<unsigned short*>(As[b]);
-      unsigned short* Bs16 = reinterpret_cast<unsigned short*>(Bs[b]);
+      if constexpr (PLANES) {  // 8 slices of one plane per 16-byte store
 #pragma unroll
-      for (int e = 0; e < G::AE; ++e) {
-        const int o = g.a_lds_row(e) * LD + g.a_lds_k(e);
+        for (int s = 0; s < NS; ++s) {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) As16[s * MT * LD + o] = (unsigned short)(g.ra[e] >> (16 * s));
-      }
+          for (int j = 0; j < G::AJ; ++j) {
+            const int r = g.lds_row(j);
+            *reinterpret_cast<u4_t*>(&As[b][s * MT * LD + r * LD + 8 * ((g.lds_k(j) / 8) ^ lds_swizzle(r))]) = g.ra[s][j];
+          }
 #pragma unroll
-      for (int e = 0; e < G::BE; ++e) {
-        const int o = g.b_lds_row(e) * LD + g.b_lds_k(e);
+          for (int j = 0; j < G::BJ; ++j) {
+            const int r = g.lds_row(j);
+            *reinterpret_cast<u4_t*>(&Bs[b][s * NT * LD + r * LD + 8 * ((g.lds_k(j) / 8) ^ lds_swizzle(r))]) = g.rb[s][j];
+          }
+        }
+      } else {  // one packed element: its NS slices to NS planes
+        unsigned short* As16 = reinterpret_cast<unsigned short*>(As[b]);
+        unsigned short* Bs16 = reinterpret_cast<unsigned short*>(Bs[b]);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) Bs16[s * NT * LD + o] = (unsigned short)(g.rb[e] >> (16 * s));
+        for (int e = 0; e < G::AE; ++e) {
+          const int o = g.a_lds_row(e) * LD + g.a_lds_k(e);
+#pragma unroll
+          for (int s = 0; s < NS; ++s) As16[s * MT * LD + o] = (unsigned short)(g.ra[e] >> (16 * s));
+        }
+#pragma unroll
+        for (int e = 0; e < G::BE; ++e) {
+          const int o = g.b_lds_row(e) * LD + g.b_lds_k(e);
+#pragma unroll
+          for (int s = 0; s < NS; ++s) Bs16[s * NT * LD + o] = (unsigned short)(g.rb[e] >> (16 * s));
+        }
       }
     };
     auto compute = [&](int b, bool flush, auto&& stage) {
@@ -344,10 +506,10 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
         for (int s = 0; s < NS; ++s) {
 #pragma unroll
           for (int i = 0; i < FM; ++i)
-            af[s][i] = *reinterpret_cast<const bf8_t*>(&As[b][s * MT * LD + a_frag + i * 16 * LD + 32 * st]);
+            af[s][i] = *reinterpret_cast<const bf8_t*>(&As[b][s * MT * LD + a_frag[i] + 32 * st]);
 #pragma unroll
           for (int j = 0; j < FN; ++j)
-            bfr[s][j] = *reinterpret_cast<const bf8_t*>(&Bs[b][s * NT * LD + b_frag + j * 16 * LD + 32 * st]);
+            bfr[s][j] = *reinterpret_cast<const bf8_t*>(&Bs[b][s * NT * LD + b_frag[j] + 32 * st]);
         }
 #pragma unroll
         for (int i = 0; i < FM; ++i)
@@ -437,10 +599,11 @@ template <int MT, int NT, int KT, int WGM, int WGN, bool AL>
 static hipError_t launch_bf(int layout, const ContractParams& p, hipStream_t s) {
   const dim3 g(p.n_work), b(64 * WGM * WGN);
   switch (layout) {
-    case 3: hipLaunchKernelGGL((k_contract_bf16s<MT, NT, KT, WGM, WGN, AL, true, true>), g, b, 0, s, p); break;
-    case 2: hipLaunchKernelGGL((k_contract_bf16s<MT, NT, KT, WGM, WGN, AL, true, false>), g, b, 0, s, p); break;
-    case 1: hipLaunchKernelGGL((k_contract_bf16s<MT, NT, KT, WGM, WGN, AL, false, true>), g, b, 0, s, p); break;
-    default: hipLaunchKernelGGL((k_contract_bf16s<MT, NT, KT, WGM, WGN, AL, false, false>), g, b, 0, s, p); break;
+    case kPlanesLayout: hipLaunchKernelGGL((k_contract_bf16s<MT, NT, KT, WGM, WGN, AL, false, false, true>), g, b, 0, s, p); break;
+    case 3: hipLaunchKernelGGL((k_contract_bf16s<MT, NT, KT, WGM, WGN, AL, true, true, false>), g, b, 0, s, p); break;
+    case 2: hipLaunchKernelGGL((k_contract_bf16s<MT, NT, KT, WGM, WGN, AL, true, false, false>), g, b, 0, s, p); break;
+    case 1: hipLaunchKernelGGL((k_contract_bf16s<MT, NT, KT, WGM, WGN, AL, false, true, false>), g, b, 0, s, p); break;
+    default: hipLaunchKernelGGL((k_contract_bf16s<MT, NT, KT, WGM, WGN, AL, false, false, false>), g, b, 0, s, p); break;
   }
   return hipGetLastError();
 }

@@ -30,12 +30,17 @@ static_assert(sizeof(PrepBlock) == 40, "PrepBlock layout");
 
 struct PrepParams {
   const double* x;        // float64 operand
-  uint64_t* out;          // packed bfloat16 slices, same element offsets as x
+  void* out;              // packed: one 64-bit word of slices per element at x's element offsets;
+                          // planes: bfloat16 slice s of block b's element (row, k) at
+                          // out[s * plane_stride + off_b + row * kext_b + k]
   const PrepBlock* blocks;
   const int32_t* pool;
   int64_t n_items;
+  int64_t plane_stride;   // planes layout: elements per slice plane
   int32_t n_blocks;
   int32_t aligned;        // 1: aligned lead + 3 residual slices, 0: 3 plain slices
+  int32_t planes;         // 1: planes layout, 0: packed
+  int32_t pad;
 };
 
 struct MixedConfig {
@@ -47,6 +52,8 @@ int mixed_config_count(int precision);
 const MixedConfig& mixed_config(int precision, int id);
 
 hipError_t launch_prep_split(const PrepParams& p, bool rows_along_lanes, hipStream_t s);
+// layout: bits 0-1 as for the float64 kernels; kPlanesLayout: split operands in planes layout.
+constexpr int kPlanesLayout = 8;
 hipError_t launch_contract_mixed(int precision, int config, int layout, const ContractParams& p, hipStream_t s);
 
 }  // namespace tamm

@@ -96,6 +96,7 @@ struct tamm_plan {
   std::vector<int> k_lhs_order;    // for each K label in lhs order: its position in K
   bool a_kc = true, b_kc = true;
   bool pairs = false;              // every gathered pair of table entries is adjacent (16-byte loads)
+  bool planes = false;             // split-bfloat16 operands in the planes layout
   std::vector<int32_t> pool;
   ScreenDesc sd{};                 // device pointers filled when bound
   int64_t n_kt = 1;
@@ -125,7 +126,9 @@ static int configure_work(tamm_plan* p, int config, int k_splits);
 
 // Gather layout index of a plan's kernels: bit 1 = A k-contiguous, bit 0 = B k-contiguous,
 // bit 2 = 16-byte (two-element) gathers.
-static int gather_layout(const tamm_plan* p) { return 2 * (p->a_kc ? 1 : 0) + (p->b_kc ? 1 : 0) + (p->pairs ? 4 : 0); }
+static int gather_layout(const tamm_plan* p) {
+  return 2 * (p->a_kc ? 1 : 0) + (p->b_kc ? 1 : 0) + (p->pairs ? 4 : 0) + (p->planes ? 8 : 0);
+}
 constexpr int kLayouts = 8;
 
 static Layout make_layout(const tamm_plan* p, size_t base) {
@@ -363,6 +366,11 @@ extern "C" int tamm_plan_create(tamm_tensor* out, const char* out_lbl, const tam
     };
     prep_list(ai, aM, aK, p->M, p->a_kc, p->prepA, p->prepA_items);
     prep_list(bi, bN, bK, p->N, p->b_kc, p->prepB, p->prepB_items);
+    // planes layout (16-byte gathers of 8 consecutive k) when every block's K extent is a
+    // multiple of 8; otherwise the packed layout at the float64 offsets
+    p->planes = true;
+    for (const auto* list : {&p->prepA, &p->prepB})
+      for (const PrepBlock& pb : *list) p->planes = p->planes && pb.kext % 8 == 0;
   }
   ScreenDesc& sd = p->sd;
   memset(&sd, 0, sizeof(sd));
@@ -767,6 +775,8 @@ static int contract_launch(tamm_plan* p, double alpha, double beta, hipStream_t 
       pa.n_items = p->prepA_items;
       pa.n_blocks = (int32_t)p->prepA.size();
       pa.aligned = p->prec == TAMM_PREC_BF16X4_ALIGNED ? 1 : 0;
+      pa.planes = p->planes ? 1 : 0;
+      pa.plane_stride = p->A->numel;
       HIP_TRY(launch_prep_split(pa, !p->a_kc, s));
       PrepParams pbp = pa;
       pbp.x = p->B->dev;
@@ -774,11 +784,17 @@ static int contract_launch(tamm_plan* p, double alpha, double beta, hipStream_t 
       pbp.blocks = (const PrepBlock*)(p->ws + p->off_prepB);
       pbp.n_items = p->prepB_items;
       pbp.n_blocks = (int32_t)p->prepB.size();
+      pbp.plane_stride = p->B->numel;
       HIP_TRY(launch_prep_split(pbp, !p->b_kc, s));
       cp.single.A = (const double*)(p->ws + p->off_xA);
       cp.single.B = (const double*)(p->ws + p->off_xB);
+      if (p->planes) {
+        cp.single.a_plane = p->A->numel;
+        cp.single.b_plane = p->B->numel;
+      }
     }
-    HIP_TRY(launch_contract_mixed(p->prec, p->config, layout & 3, cp, s));
+    const bool planes = p->planes && p->prec != TAMM_PREC_F32;
+    HIP_TRY(launch_contract_mixed(p->prec, p->config, planes ? kPlanesLayout : (layout & 3), cp, s));
   }
   if (p->k_splits > 1) {
     const TileCfg f = cfg_get(p->prec, p->config);

@@ -58,6 +58,18 @@ def test_mixed_every_config_with_splits(precision):
             assert rel <= TOL[precision], (precision, plan.config_name(), ks, rel)
 
 
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16x4_aligned"])
+@pytest.mark.parametrize("shape,planes", [((24, 40, 12, 16), True), ((22, 38, 11, 15), False)], ids=["planes", "packed"])
+@pytest.mark.parametrize("term", ["ladder", "ring", "hh", "hh_int"])
+def test_split_layouts(precision, shape, planes, term):
+    # K extents that are multiples of 8 use the slice-plane layout, others the packed layout
+    prob = Problem(*shape)
+    got, ref, plan = run(prob, term, precision)
+    assert bool(plan.stats()["gather_layout"] & 8) == planes
+    rel, _ = max_rel(got, ref)
+    assert rel <= TOL[precision], (precision, term, rel)
+
+
 def test_aligned_split_windows_longer_than_one():
     # pairs whose K extent spans several 256-long windows (tiles of 32 -> K = 1024 per pair)
     prob = Problem(16, 64, 8, 32)
