@@ -21,6 +21,7 @@ ladder contraction) and the oracle's CPU throughput on a bounded sample are repo
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -192,24 +193,37 @@ def main():
         if evs is not None:
             evs["denominator"][1].record(stream)
 
-    for _ in range(args.warmup):
-        step(None)
-    torch.cuda.synchronize()
-    log(f"[bench] warmup done ({args.warmup} steps)")
     keys = STEP_TERMS + ["ladder_kernel", "denominator"]
     events = [{k: (new_ev(), new_ev()) for k in keys} for _ in range(args.steps)]
     t0 = new_ev()
     t1 = new_ev()
+    # no garbage collection from the warm-up to the end of the timed region: a collection pass
+    # on the host while the launch queue is empty would stall the launches
+    gc.collect()
+    gc.disable()
+    for _ in range(args.warmup):
+        step(None)
     torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup} steps)")
+    torch.cuda.synchronize()
+    h0 = time.perf_counter()
     t0.record(stream)
     for i in range(args.steps):
         step(events[i])
     t1.record(stream)
+    h1 = time.perf_counter()
     torch.cuda.synchronize()
+    gc.enable()
+    log(f"[bench] host enqueue of the timed steps: {(h1 - h0) * 1e3:.1f} ms")
     total_ms = t0.elapsed_time(t1)
     ms_per_step = total_ms / args.steps
     acc = {k: sum(e[k][0].elapsed_time(e[k][1]) for e in events) for k in keys}
-    log(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step")
+    # per-step span (first term's start to the denominator's end), to expose outliers
+    spans = [e[STEP_TERMS[0]][0].elapsed_time(e["denominator"][1]) for e in events]
+    log(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step; per step " +
+        " ".join(f"{x:.2f}" for x in spans))
+    for t in STEP_TERMS:
+        log(f"[bench]   {t}: " + " ".join(f"{e[t][0].elapsed_time(e[t][1]):.3f}" for e in events))
 
     flops = {t: plans[t].stats()["useful_flops"] for t in STEP_TERMS}
     step_flops = sum(flops.values())
@@ -250,6 +264,8 @@ def main():
                    "tile_occ": wl["tile_occ"], "tile_vir": wl["tile_vir"], "terms": STEP_TERMS,
                    "precision": "f64", "includes": "screening + contraction per term, denominator update",
                    "configs": "autotuned" if not args.no_tune else "default"},
+        "step_ms_min": round(min(spans), 4),
+        "step_ms_max": round(max(spans), 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "terms": per_term,
@@ -617,6 +633,11 @@ def run_adjoint(args):
         _, L = fwd()
         L.backward()
 
+    if not args.no_tune:
+        fwd_bwd()  # builds the forward and both gradient plans
+        torch.cuda.synchronize()
+        for c in (lad, ring):
+            c.autotune(args.tune_cache)
     f_ms = _time(torch, fwd_only, args.steps, args.warmup)
     fb_ms = _time(torch, fwd_bwd, args.steps, args.warmup)
     fl_f = sum(p.stats()["useful_flops"] for c in (lad, ring) for k, p in c._plans.items() if k == "fwd")
@@ -630,8 +651,9 @@ def run_adjoint(args):
 
 
 def run_copycal(args):
-    """A plain device copy of known size (torch's copy kernel): the calibration run for the HBM
-    traffic counters (FETCH_SIZE / WRITE_SIZE per dispatch against known bytes)."""
+    """A plain device-to-device copy of known size (torch's copy_, which runs the HIP runtime's
+    copy kernel): the calibration run for the HBM traffic counters (FETCH_SIZE / WRITE_SIZE per
+    dispatch against known bytes)."""
     import torch
 
     n = 1 << 28  # 2 GiB of float64 read, 2 GiB written per dispatch

@@ -62,6 +62,12 @@ class Contraction:
             tm.check(tm.load().tamm_plan_bind_workspace(p._h, tm.ctypes.c_void_p(ptr), p.workspace_size()))
         p.execute(alpha, beta)
 
+    def autotune(self, cache_path: str = "", reps: int = 2):
+        """Run the library's autotuner on every plan built so far (forward and, after a backward
+        pass, both gradient plans) on the storages of the last call; outputs are left unchanged."""
+        for p in self._plans.values():
+            p.autotune(cache_path, reps=reps)
+
     def __call__(self, lhs_data: torch.Tensor, rhs_data: torch.Tensor, out0_data: Optional[torch.Tensor] = None):
         return _ContractFn.apply(lhs_data, rhs_data, out0_data, self)
 
