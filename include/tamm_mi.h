@@ -247,19 +247,25 @@ int tamm_group_workspace_size(const tamm_group* g, size_t* bytes);
  * (synchronous).  Drops a captured graph. */
 int tamm_group_bind_workspace(tamm_group* g, void* dev_ptr, size_t bytes);
 /* Select the kernel configuration (-1 = default) and the persistent grid size (0 = every
- * resident slot: compute units x workgroups of the configuration that fit on one).  Requires re-querying the workspace size and re-binding. */
+ * resident slot: compute units x workgroups of the configuration that fit on one).  Requires
+ * re-querying the workspace size and re-binding. */
 int tamm_group_set_config(tamm_group* g, int32_t config, int32_t grid);
 /* alpha and beta are host arrays of n values, read during the call.  If a graph was captured
  * with the same alpha/beta and the members' storage bindings are unchanged, the graph is
- * replayed; otherwise the kernels are launched directly (and any graph is dropped). */
+ * replayed; otherwise the kernels are launched directly (and any graph is dropped).  When the
+ * coefficients or bindings differ from the previous call, the per-member descriptors in the
+ * workspace are rewritten first: the stream is synchronised and the copy is synchronous (earlier
+ * launches may still read the old descriptors); calls with unchanged values launch
+ * asynchronously. */
 int tamm_group_execute(tamm_group* g, const double* alpha, const double* beta, void* stream);
 /* Capture the group's launches (counter reset, screening, persistent contraction; no memset or
  * copy nodes) into a hipGraph on an internal stream, with alpha/beta fixed at these values;
  * later tamm_group_execute calls with the same values replay it on their stream. */
 int tamm_group_capture(tamm_group* g, const double* alpha, const double* beta, void* stream);
 /* Autotuner for groups: every kernel configuration with persistent grids of 1, 2 and 4
- * workgroups per compute unit and the occupancy-sized grid, timed on stream with alpha = 0, beta = 1; keeps the fastest and
- * caches it in cache_path (if non-empty) under the group's structural signature.  Needs a
+ * workgroups per compute unit and the occupancy-sized grid, timed on stream with alpha = 0,
+ * beta = 1; keeps the fastest and caches it in cache_path (if non-empty) under the group's
+ * structural signature.  Needs a
  * bound workspace large enough for the candidates (candidates that do not fit are skipped).
  * Synchronises the stream. */
 int tamm_group_autotune(tamm_group* g, void* stream, const char* cache_path, int32_t reps);
