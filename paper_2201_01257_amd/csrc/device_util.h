@@ -230,8 +230,8 @@ struct Gather {
 // registers since the previous chunk) into the other buffer and issues the global loads of
 // chunk c+2 into the same registers.  stage() has no branch, so the compiler can interleave its
 // LDS stores and global loads with the MFMAs; past the last chunk it moves data nobody reads.
-// The bookkeeping that does branch (the next chunk's pair, its table entries) runs between the
-// barrier and the next chunk.  `flush` tells compute that chunk c ends a promotion window of W
+// The bookkeeping that does branch (the next chunk's pair, its table entries) runs in the
+// post() callback, which compute calls once its last MFMA is issued.  `flush` tells compute that chunk c ends a promotion window of W
 // summed indices or a pair (W = 0: pairs only); the flags travel with the chunks in a FIFO.
 // Chunks run over pairs [pb, pe) and KT-long pieces of each.
 template <int KT, int W, typename G, typename T, typename StoreF, typename ComputeF>
@@ -279,14 +279,20 @@ __device__ __forceinline__ void chunk_pipeline(G& g, const PairDesc* pairs, int 
     const bool flush = (fifo & 1u) != 0;
     fifo >>= 1;
     --nf;
-    compute(buf, flush, [&]() {
-      store(buf ^ 1);
-      g.load_data();
-    });
+    bool tabs_next = false;
+    compute(
+        buf, flush,
+        [&]() {  // after the first k-step: the next chunk to LDS, the loads of the one after it
+          store(buf ^ 1);
+          g.load_data();
+        },
+        [&]() {  // after the last MFMA is issued: the bookkeeping runs while the MFMAs drain
+          tabs_next = tabs && advance();
+        });
     __syncthreads();  // buffer `buf` is free again; the other one holds the next chunk
     if (!inflight) break;
-    inflight = tabs;  // the loads just issued carried a real chunk
-    tabs = tabs && advance();
+    inflight = tabs;  // the loads issued in this chunk carried a real chunk
+    tabs = tabs_next;
     buf ^= 1;
   }
 }

@@ -151,7 +151,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (int e = 0; e < G::BE; ++e) Bs[b][g.b_lds_row(e) * LD + g.b_lds_k(e)] = g.rb[e];
       };
-      auto compute = [&](int b, bool, auto&& stage) {
+      auto compute = [&](int b, bool, auto&& stage, auto&& post) {
         const double* as = As[b] + a_frag;
         const double* bs = Bs[b] + b_frag;
         double af[2][FM], bf[2][FN];
@@ -177,6 +177,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
           if (s == 0) stage();
         }
         __builtin_amdgcn_s_setprio(0);
+        post();
       };
       chunk_pipeline<KT, 0>(g, pairs, pb, pe, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next, store, compute);
     }

@@ -290,7 +290,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
 #pragma unroll
       for (int e = 0; e < G::BE; ++e) Bs[b][g.b_lds_row(e) * LD + g.b_lds_k(e)] = (float)g.rb[e];
     };
-    auto compute = [&](int b, bool flush, auto&& stage) {
+    auto compute = [&](int b, bool flush, auto&& stage, auto&& post) {
       const float* as = As[b] + a_frag;
       const float* bs = Bs[b] + b_frag;
       float af[2][FM], bf[2][FN];
@@ -316,6 +316,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
         if (s == 0) stage();
       }
       __builtin_amdgcn_s_setprio(0);
+      post();  // bookkeeping of the next chunk while the MFMAs drain
       if (flush) {  // end of a promotion window or of a pair: float32 sums into float64
 #pragma unroll
         for (int i = 0; i < FM; ++i)
@@ -497,7 +498,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
         }
       }
     };
-    auto compute = [&](int b, bool flush, auto&& stage) {
+    auto compute = [&](int b, bool flush, auto&& stage, auto&& post) {
       __builtin_amdgcn_s_setprio(1);
 #pragma unroll
       for (int st = 0; st < KT / 32; ++st) {  // zeros beyond a ragged chunk's K extent
@@ -541,6 +542,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
         if (st == 0) stage();
       }
       __builtin_amdgcn_s_setprio(0);
+      post();  // bookkeeping of the next chunk while the MFMAs drain
       if (flush) {  // end of a promotion window or of a pair: float32 sums into float64
 #pragma unroll
         for (int i = 0; i < FM; ++i)
