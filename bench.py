@@ -157,7 +157,7 @@ def main():
         # split of each plan is timed on the real operands and the fastest kept
         t0 = time.time()
         for term in STEP_TERMS:
-            plans[term].autotune(args.tune_cache, reps=2)
+            plans[term].autotune(args.tune_cache, reps=3)
             st = plans[term].stats()
             log(f"[bench] tuned {term}: config {plans[term].config_name()} k_splits {st['k_splits']} "
                 f"work {st['work_items']}")

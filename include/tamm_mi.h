@@ -191,18 +191,22 @@ typedef struct {
 int tamm_plan_stats_get(const tamm_plan* p, tamm_plan_stats* s);
 
 /* Kernel configurations available for this plan's precision: *count receives the number; ids
- * are 0..count-1.  tamm_plan_set_config selects one (the autotuner uses this) and k_splits
- * >= 1 splits each output tile's K range into that many deterministic partial sums (0 = let
- * the library choose).  Changing the configuration requires re-querying the workspace size
- * and re-binding. */
+ * are 0..count-1.  tamm_plan_set_config selects one (the autotuner uses this); k_splits >= 1
+ * splits the pair range of the output tiles of the heaviest blocks (largest summed K extent)
+ * into that many deterministic partial sums, and lighter blocks' tiles into proportionally
+ * fewer (at least one); 0 lets the library choose.  Changing the configuration requires
+ * re-querying the workspace size and re-binding. */
 int tamm_plan_config_count(const tamm_plan* p, int32_t* count);
 int tamm_plan_set_config(tamm_plan* p, int32_t config, int32_t k_splits);
-/* Human-readable name of a configuration (static string), e.g. "f64_m128n64k16_w2x2". */
+/* Human-readable name of a configuration (static string), e.g. "f64_m128n64k16_w2x2_o1". */
 const char* tamm_config_name(int32_t precision, int32_t config);
 
 /* Autotuner.  Measures every kernel configuration with K splits 1, 2, 4 and 8 that fits the
- * given workspace (hipEvents on stream, `reps` timed executions after one warm-up; reps <= 0
- * means 3), keeps the fastest, and leaves the plan configured and bound to `workspace`.  The
+ * given workspace (hipEvents on stream; after one warm-up, the fastest of `reps` individually
+ * timed executions counts; reps <= 0 means 3), keeps the fastest, and leaves the plan configured
+ * and bound to `workspace`.  With K splits s > 1 the tiles of the blocks with the largest summed
+ * K extent are split into s parts and lighter blocks' tiles into proportionally fewer (at least
+ * one), so the parts cost about the same.  The
  * trial executions run with alpha = 0, beta = 1, so out keeps its values when the operands are
  * finite.  With a non-empty cache_path the result is appended to that text file keyed by the
  * plan's structural signature, and a later call with the same structure reuses it without

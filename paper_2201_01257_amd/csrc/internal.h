@@ -47,16 +47,23 @@ struct PairDesc {
 };
 static_assert(sizeof(PairDesc) == 40, "PairDesc layout");
 
-// One output macro-tile (or one K split of it) processed by one workgroup.
+// One output macro-tile (or one K split of it) processed by one workgroup.  A tile split into
+// nsplit > 1 parts (each a contiguous range of its block's surviving pairs) writes partial tiles
+// to workspace slots tile .. tile + nsplit - 1, which k_reduce sums in order; an unsplit tile
+// runs the epilogue itself.
 struct WorkItem {
   int32_t prob;   // problem index inside a group (0 for a single plan)
   int32_t ob;     // output block
   int32_t m0;     // first flattened row of the tile
   int32_t n0;     // first flattened column
-  int32_t split;  // K split index (0 .. k_splits-1)
-  int32_t tile;   // index of the output tile inside its problem (partial-tile addressing)
+  int32_t split;  // split index in bits 0-15, number of splits of the tile in bits 16-30 (0 = 1)
+  int32_t tile;   // first partial-tile slot of the tile (split tiles only)
 };
 static_assert(sizeof(WorkItem) == 24, "WorkItem layout");
+
+__host__ __device__ inline int32_t item_split(const WorkItem& w) { return w.split & 0xFFFF; }
+__host__ __device__ inline int32_t item_nsplit(const WorkItem& w) { return (w.split >> 16) > 1 ? (w.split >> 16) : 1; }
+__host__ __device__ inline int32_t encode_split(int32_t split, int32_t nsplit) { return split | (nsplit << 16); }
 
 // Everything the contraction kernel needs about one contraction.
 struct ProblemDesc {
@@ -121,7 +128,9 @@ struct ScreenParams {
 };
 
 struct ReduceItem {
-  int32_t prob, ob, m0, n0, tile, pad;
+  int32_t prob, ob, m0, n0;
+  int32_t tile;    // first partial-tile slot
+  int32_t nsplit;  // partial tiles to sum, in slot order
 };
 
 struct ReduceParams {

@@ -132,11 +132,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
     const int32_t* __restrict__ pool = pr.pool;
     const PairDesc* __restrict__ pairs = pr.pairs + blk.pair_base;
     const int cnt = wave_uniform(gload(pr.counts + w.ob));
-    int pb = 0, pe = cnt;
-    if (pr.k_splits > 1) {
-      pb = (int)(((int64_t)cnt * w.split) / pr.k_splits);
-      pe = (int)(((int64_t)cnt * (w.split + 1)) / pr.k_splits);
-    }
+    const int nsplit = item_nsplit(w), split = item_split(w);
+    const int pb = (int)(((int64_t)cnt * split) / nsplit), pe = (int)(((int64_t)cnt * (split + 1)) / nsplit);
 
     d4_t acc[FM][FN];
 #pragma unroll
@@ -183,8 +180,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
     }
 
     // epilogue: lane holds D[m][n] for m = 4r + lane/16 (register r), n = lane%16
-    if (pr.k_splits > 1) {
-      double* part = pr.partial + ((int64_t)w.tile * pr.k_splits + w.split) * (MT * NT);
+    if (nsplit > 1) {
+      double* part = pr.partial + ((int64_t)w.tile + split) * (MT * NT);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -240,12 +237,12 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceParams P) {
   const ProblemDesc& pr = P.probs ? P.probs[it.prob] : P.single;
   const OutBlockDesc blk = pr.blocks[it.ob];
   const int tile = P.tile_m * P.tile_n;
-  const double* part = pr.partial + (int64_t)it.tile * pr.k_splits * tile;
+  const double* part = pr.partial + (int64_t)it.tile * tile;
   for (int e = threadIdx.x; e < tile; e += blockDim.x) {
     const int m = it.m0 + e / P.tile_n, n = it.n0 + e % P.tile_n;
     if (m >= blk.mext || n >= blk.next) continue;
     double s = 0.0;
-    for (int k = 0; k < pr.k_splits; ++k) s += part[(int64_t)k * tile + e];
+    for (int k = 0; k < it.nsplit; ++k) s += part[(int64_t)k * tile + e];
     const int64_t idx = blk.c_off + pr.pool[blk.c_tabM + m] + pr.pool[blk.c_tabN + n];
     const double v = pr.alpha * s;
     pr.C[idx] = (pr.beta == 0.0) ? v : pr.beta * pr.C[idx] + v;

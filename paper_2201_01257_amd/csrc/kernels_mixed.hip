@@ -214,8 +214,8 @@ hipError_t launch_prep_split(const PrepParams& p, bool rows_along_lanes, hipStre
 template <int MT, int NT, int WM, int WN, int FM, int FN>
 __device__ __forceinline__ void epilogue_f32layout(const ProblemDesc& pr, const WorkItem& w, const OutBlockDesc& blk,
                                                    d4_t (&acc)[FM][FN], int wm, int wn, int lr, int lq) {
-  if (pr.k_splits > 1) {
-    double* part = pr.partial + ((int64_t)w.tile * pr.k_splits + w.split) * (MT * NT);
+  if (item_nsplit(w) > 1) {
+    double* part = pr.partial + ((int64_t)w.tile + item_split(w)) * (MT * NT);
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -267,11 +267,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
   const int32_t* __restrict__ pool = pr.pool;
   const PairDesc* __restrict__ pairs = pr.pairs + blk.pair_base;
   const int cnt = wave_uniform(gload(pr.counts + w.ob));
-  int pb = 0, pe = cnt;
-  if (pr.k_splits > 1) {
-    pb = (int)(((int64_t)cnt * w.split) / pr.k_splits);
-    pe = (int)(((int64_t)cnt * (w.split + 1)) / pr.k_splits);
-  }
+  const int nsplit = item_nsplit(w), split = item_split(w);
+  const int pb = (int)(((int64_t)cnt * split) / nsplit), pe = (int)(((int64_t)cnt * (split + 1)) / nsplit);
   G g;
   g.init(tid);
   d4_t acc[FM][FN];
@@ -447,11 +444,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
   const E* Ap = reinterpret_cast<const E*>(pr.A);
   const E* Bp = reinterpret_cast<const E*>(pr.B);
   const int cnt = wave_uniform(gload(pr.counts + w.ob));
-  int pb = 0, pe = cnt;
-  if (pr.k_splits > 1) {
-    pb = (int)(((int64_t)cnt * w.split) / pr.k_splits);
-    pe = (int)(((int64_t)cnt * (w.split + 1)) / pr.k_splits);
-  }
+  const int nsplit = item_nsplit(w), split = item_split(w);
+  const int pb = (int)(((int64_t)cnt * split) / nsplit), pe = (int)(((int64_t)cnt * (split + 1)) / nsplit);
   G g;
   if constexpr (PLANES) g.init(tid, pr.a_plane, pr.b_plane);
   else g.init(tid);

@@ -621,14 +621,33 @@ static int configure_work(tamm_plan* p, int config, int k_splits) {
       for (int32_t n0 = 0; n0 < d.next; n0 += f.nt)
         tiles.push_back(Tile{p->block_cost[b] * std::min(f.mt, d.mext - m0) * std::min(f.nt, d.next - n0), (int32_t)b, m0, n0});
   }
-  std::stable_sort(tiles.begin(), tiles.end(), [](const Tile& x, const Tile& y) { return x.cost > y.cost; });
-  p->work.clear();
+  // K splits per tile in proportion to its block's summed K extent: tiles of the heaviest blocks
+  // get k_splits parts, lighter ones fewer (at least one), so that the parts cost about the same
+  double max_cost = 0;
+  for (const Tile& t : tiles) max_cost = std::max(max_cost, p->block_cost[t.ob]);
+  struct Part {
+    double cost;
+    WorkItem w;
+  };
+  std::vector<Part> parts;
   p->reduce.clear();
-  for (size_t t = 0; t < tiles.size(); ++t) {
-    for (int s = 0; s < k_splits; ++s)
-      p->work.push_back(WorkItem{0, tiles[t].ob, tiles[t].m0, tiles[t].n0, s, (int32_t)t});
-    if (k_splits > 1) p->reduce.push_back(ReduceItem{0, tiles[t].ob, tiles[t].m0, tiles[t].n0, (int32_t)t, 0});
+  int64_t slots = 0;
+  for (const Tile& t : tiles) {
+    int ns = 1;
+    if (k_splits > 1 && max_cost > 0)
+      ns = (int)std::min<double>(k_splits, std::max(1.0, std::floor(k_splits * p->block_cost[t.ob] / max_cost + 0.5)));
+    for (int s = 0; s < ns; ++s)
+      parts.push_back(Part{t.cost / ns, WorkItem{0, t.ob, t.m0, t.n0, encode_split(s, ns), (int32_t)slots}});
+    if (ns > 1) {
+      p->reduce.push_back(ReduceItem{0, t.ob, t.m0, t.n0, (int32_t)slots, ns});
+      slots += ns;
+    }
+    if (slots > INT32_MAX / 2) return fail(TAMM_ERR_UNSUPPORTED, "too many partial tiles");
   }
+  // longest processing time first; the parts of a tile stay adjacent when their costs tie
+  std::stable_sort(parts.begin(), parts.end(), [](const Part& x, const Part& y) { return x.cost > y.cost; });
+  p->work.clear();
+  for (const Part& q : parts) p->work.push_back(q.w);
   if (p->work.size() > (size_t)INT32_MAX / 2) return fail(TAMM_ERR_UNSUPPORTED, "too many work items");
   xcd_order(p->work, xcd_chunk());
   p->config = config;
@@ -644,7 +663,7 @@ static int configure_work(tamm_plan* p, int config, int k_splits) {
   p->off_reduce = off;
   off = align256(off + p->reduce.size() * sizeof(ReduceItem));
   p->off_partial = off;
-  if (k_splits > 1) off = align256(off + tiles.size() * (size_t)k_splits * f.mt * f.nt * sizeof(double));
+  if (slots > 0) off = align256(off + (size_t)slots * f.mt * f.nt * sizeof(double));
   if (p->prec == TAMM_PREC_BF16X3 || p->prec == TAMM_PREC_BF16X4_ALIGNED) {
     p->off_prepA = off;
     off = align256(off + p->prepA.size() * sizeof(PrepBlock));
@@ -927,16 +946,20 @@ extern "C" int tamm_plan_autotune(tamm_plan* p, void* workspace, size_t bytes, v
         if (ks > 1 && nt * ks > 4 * std::max<int64_t>(ntiles_max, 2048)) continue;
         if (configure_work(p, c, ks) != TAMM_OK || p->ws_size > bytes) continue;
         if ((rc = bind_plan(p, workspace, bytes)) != TAMM_OK) break;
-        // alpha = 0, beta = 1 leaves out unchanged (for finite operands) while doing the full work
+        // alpha = 0, beta = 1 leaves out unchanged (for finite operands) while doing the full work;
+        // the fastest of `reps` timed executions counts (robust against clock and queue noise)
         if ((rc = tamm_plan_execute(p, 0.0, 1.0, stream)) != TAMM_OK) break;
-        HIP_TRY(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r)
-          if ((rc = tamm_plan_execute(p, 0.0, 1.0, stream)) != TAMM_OK) break;
-        HIP_TRY(hipEventRecord(e1, s));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        ms /= reps;
+        float ms = 1e30f;
+        for (int r = 0; r < reps && rc == TAMM_OK; ++r) {
+          HIP_TRY(hipEventRecord(e0, s));
+          rc = tamm_plan_execute(p, 0.0, 1.0, stream);
+          HIP_TRY(hipEventRecord(e1, s));
+          HIP_TRY(hipEventSynchronize(e1));
+          float one = 0;
+          HIP_TRY(hipEventElapsedTime(&one, e0, e1));
+          ms = std::min(ms, one);
+        }
+        if (rc != TAMM_OK) break;
         if (ms < best.ms) best = CacheEntry{c, ks, 0, ms};
       }
       if (rc != TAMM_OK) break;
