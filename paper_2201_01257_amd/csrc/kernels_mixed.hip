@@ -35,14 +35,17 @@ typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------------------------
 // operand split
 // ---------------------------------------------------------------------------------------------
-// Round to nearest even at 8 significant bits (the bfloat16 precision), in float64 arithmetic.
-// Magnitudes below 2^-100 are flushed to zero (far below anything the slices can carry).
+// Round to nearest even at 8 significant bits (the bfloat16 precision), on the float64 bit pattern:
+// adding half a unit of the kept part (less one ulp when the kept part is even) and clearing the
+// 45 dropped mantissa bits rounds to nearest even; a carry out of the mantissa steps the exponent,
+// which is the correctly rounded result.  Magnitudes below 2^-100 are flushed to zero (far below
+// anything the slices can carry).  Finite inputs only.
 __device__ __forceinline__ double round_bf16(double x) {
-  const double ax = fabs(x);
-  if (!(ax >= 0x1p-100)) return 0.0;
-  const int e = ilogb(x);
-  const double q = ldexp(1.0, e - 7);
-  return rint(x / q) * q;
+  uint64_t u = __builtin_bit_cast(uint64_t, x);
+  if (((u >> 52) & 0x7FF) < 1023 - 100) return 0.0;
+  u += 0x00000FFFFFFFFFFFull + ((u >> 45) & 1u);
+  u &= ~0x00001FFFFFFFFFFFull;
+  return __builtin_bit_cast(double, u);
 }
 
 // Bits of a value that is exactly representable in bfloat16.
@@ -59,22 +62,25 @@ __device__ __forceinline__ uint64_t split_plain(double x) {
   return bf16_bits(b0) | (bf16_bits(b1) << 16) | (bf16_bits(b2) << 32);
 }
 
-// scale = 2^(e-8) where 2^e > max |x| of the (row, window)
-__device__ __forceinline__ uint64_t split_aligned(double x, double scale) {
-  const double lead = rint(x / scale) * scale;  // |lead / scale| <= 256
-  const double r = x - lead;                    // exact
+// 2^p for -1022 <= p <= 1023
+__device__ __forceinline__ double pow2(int p) { return __builtin_bit_cast(double, (uint64_t)(p + 1023) << 52); }
+
+// Grid of a (row, window) with maximum magnitude mx: the exponent e with 2^(e-1) <= mx < 2^e
+// (taken as -1000 for smaller maxima, whose slices are all zero in bfloat16 anyway); the lead
+// slice is x rounded to multiples of 2^(e-8).
+__device__ __forceinline__ int window_exponent(double mx) {
+  const int bexp = (int)((__builtin_bit_cast(uint64_t, mx) >> 52) & 0x7FF);
+  return max(bexp - 1022, -1000);
+}
+
+__device__ __forceinline__ uint64_t split_aligned(double x, int e) {
+  const double lead = rint(x * pow2(8 - e)) * pow2(e - 8);  // an integer of magnitude <= 256 times 2^(e-8)
+  const double r = x - lead;                                // exact
   const double s1 = round_bf16(r);
   const double r2 = r - s1;
   const double s2 = round_bf16(r2);
   const double s3 = round_bf16(r2 - s2);
   return bf16_bits(lead) | (bf16_bits(s1) << 16) | (bf16_bits(s2) << 32) | (bf16_bits(s3) << 48);
-}
-
-__device__ __forceinline__ double window_scale(double mx) {
-  if (!(mx > 0.0)) return 1.0;
-  int e;
-  frexp(mx, &e);  // mx = f * 2^e, f in [0.5, 1): 2^e > mx
-  return ldexp(1.0, e - 8);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -120,18 +126,33 @@ __global__ __launch_bounds__(256) void k_prep_split(PrepParams P) {
       const int64_t rowoff = pb.off + pool[pb.tab_row + row];
       static_assert(kSplitWindow == 4 * 64, "a wave converts one window, 4 k per lane");
       const int k = k0 + 4 * lane;
-      double x[4];
+      double x[4] = {0.0, 0.0, 0.0, 0.0};
+      if (k < k1) {
+        int32_t t[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) t[i] = pool[pb.tab_k + k + i];
+        const int64_t a = rowoff + t[0];
+        if (t[1] == t[0] + 1 && t[2] == t[0] + 2 && t[3] == t[0] + 3 && (a & 1) == 0) {
+          // four consecutive elements at a 16-byte boundary: two 16-byte loads
+          typedef double d2_t __attribute__((ext_vector_type(2)));
+          const d2_t lo = *reinterpret_cast<const d2_t*>(P.x + a), hi = *reinterpret_cast<const d2_t*>(P.x + a + 2);
+          x[0] = lo[0];
+          x[1] = lo[1];
+          x[2] = hi[0];
+          x[3] = hi[1];
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) x[i] = P.x[rowoff + t[i]];
+        }
+      }
       double mx = 0.0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        x[i] = (k < k1) ? P.x[rowoff + pool[pb.tab_k + k + i]] : 0.0;
-        mx = fmax(mx, fabs(x[i]));
-      }
-      const double scale = window_scale(wave_max(mx));
+      for (int i = 0; i < 4; ++i) mx = fmax(mx, fabs(x[i]));
+      const int e = window_exponent(wave_max(mx));
       if (k < k1) {
         uint64_t w[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) w[i] = P.aligned ? split_aligned(x[i], scale) : split_plain(x[i]);
+        for (int i = 0; i < 4; ++i) w[i] = P.aligned ? split_aligned(x[i], e) : split_plain(x[i]);
         const int64_t pos = pb.off + (int64_t)row * pb.kext + k;
         for (int sl = 0; sl < ns; ++sl) {
           uint64_t v = 0;
@@ -147,13 +168,13 @@ __global__ __launch_bounds__(256) void k_prep_split(PrepParams P) {
       double mx = 0.0;
       if (P.aligned)
         for (int k = k0; k < k1; ++k) mx = fmax(mx, fabs(P.x[rowoff + pool[pb.tab_k + k]]));
-      const double scale = window_scale(mx);
+      const int e = window_exponent(mx);
       for (int k = k0; k < k1; k += 8) {
         uint64_t w[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const double v = P.x[rowoff + pool[pb.tab_k + k + i]];
-          w[i] = P.aligned ? split_aligned(v, scale) : split_plain(v);
+          w[i] = P.aligned ? split_aligned(v, e) : split_plain(v);
         }
         const int64_t pos = pb.off + (int64_t)row * pb.kext + k;
         for (int sl = 0; sl < ns; ++sl) {
@@ -178,12 +199,12 @@ __global__ __launch_bounds__(256) void k_prep_split(PrepParams P) {
       x[j] = (k < k1) ? P.x[rowoff + pool[pb.tab_k + k]] : 0.0;
       mx = fmax(mx, fabs(x[j]));
     }
-    const double scale = window_scale(wave_max(mx));
+    const int e = window_exponent(wave_max(mx));
 #pragma unroll
     for (int j = 0; j < kSplitWindow / 64; ++j) {
       const int k = k0 + lane + 64 * j;
       if (k < k1)
-        static_cast<uint64_t*>(P.out)[rowoff + pool[pb.tab_k + k]] = P.aligned ? split_aligned(x[j], scale) : split_plain(x[j]);
+        static_cast<uint64_t*>(P.out)[rowoff + pool[pb.tab_k + k]] = P.aligned ? split_aligned(x[j], e) : split_plain(x[j]);
     }
   } else {
     const int row = rg * 64 + lane;
@@ -192,11 +213,11 @@ __global__ __launch_bounds__(256) void k_prep_split(PrepParams P) {
     double mx = 0.0;
     if (P.aligned)
       for (int k = k0; k < k1; ++k) mx = fmax(mx, fabs(P.x[rowoff + pool[pb.tab_k + k]]));
-    const double scale = window_scale(mx);
+    const int e = window_exponent(mx);
     for (int k = k0; k < k1; ++k) {
       const int64_t a = rowoff + pool[pb.tab_k + k];
       const double v = P.x[a];
-      static_cast<uint64_t*>(P.out)[a] = P.aligned ? split_aligned(v, scale) : split_plain(v);
+      static_cast<uint64_t*>(P.out)[a] = P.aligned ? split_aligned(v, e) : split_plain(v);
     }
   }
 }
@@ -346,9 +367,13 @@ __device__ __forceinline__ int lds_swizzle(int r) { return ((r >> 1) ^ (r >> 3))
 template <int MT, int NT, int KT, int NTHR, int NS>
 struct PlaneGather {
   static constexpr int KG = KT / 8;           // 16-byte groups per row of a chunk
-  static constexpr int AJ = MT * KG / NTHR;   // loads per plane and thread
-  static constexpr int BJ = NT * KG / NTHR;
-  static_assert(KT % 8 == 0 && MT * KG % NTHR == 0 && NT * KG % NTHR == 0, "plane gather mapping");
+  static constexpr int AJ = (MT * KG + NTHR - 1) / NTHR;  // loads per plane and thread
+  static constexpr int BJ = (NT * KG + NTHR - 1) / NTHR;
+  static_assert(KT % 8 == 0 && (MT * KG % NTHR == 0 || NTHR % (MT * KG) == 0) &&
+                    (NT * KG % NTHR == 0 || NTHR % (NT * KG) == 0), "plane gather mapping");
+  // a load slot past the tile (fewer 16-byte groups than threads): whole waves skip it
+  __device__ static bool a_live(int p) { return MT * KG % NTHR == 0 || p < MT * KG; }
+  __device__ static bool b_live(int p) { return NT * KG % NTHR == 0 || p < NT * KG; }
   static constexpr uint32_t kPast = 0x80000000u;  // byte offset beyond every block
 
   int tid;
@@ -383,12 +408,14 @@ struct PlaneGather {
 #pragma unroll
       for (int j = 0; j < AJ; ++j) {
         const int p = tid + j * NTHR, r = m0 + p / KG, k = kbase + 8 * (p % KG);
+        if (!a_live(p)) continue;
         const uint32_t off = (r < mext && k < kext) ? (uint32_t)(r * kext + k) * 2u : kPast;
         ra[sl][j] = __builtin_bit_cast(u4_t, __builtin_amdgcn_raw_buffer_load_b128(ar, (int)off, 0, 0));
       }
 #pragma unroll
       for (int j = 0; j < BJ; ++j) {
         const int p = tid + j * NTHR, r = n0 + p / KG, k = kbase + 8 * (p % KG);
+        if (!b_live(p)) continue;
         const uint32_t off = (r < next && k < kext) ? (uint32_t)(r * kext + k) * 2u : kPast;
         rb[sl][j] = __builtin_bit_cast(u4_t, __builtin_amdgcn_raw_buffer_load_b128(br, (int)off, 0, 0));
       }
@@ -466,11 +493,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
         for (int s = 0; s < NS; ++s) {
 #pragma unroll
           for (int j = 0; j < G::AJ; ++j) {
+            if (!G::a_live(tid + j * NTHR)) continue;
             const int r = g.lds_row(j);
             *reinterpret_cast<u4_t*>(&As[b][s * MT * LD + r * LD + 8 * ((g.lds_k(j) / 8) ^ lds_swizzle(r))]) = g.ra[s][j];
           }
 #pragma unroll
           for (int j = 0; j < G::BJ; ++j) {
+            if (!G::b_live(tid + j * NTHR)) continue;
             const int r = g.lds_row(j);
             *reinterpret_cast<u4_t*>(&Bs[b][s * NT * LD + r * LD + 8 * ((g.lds_k(j) / 8) ^ lds_swizzle(r))]) = g.rb[s][j];
           }
@@ -563,11 +592,17 @@ static const MixedConfig kF32Configs[] = {
     {128, 64, 16, 2, 2, "f32_m128n64k16_w2x2"},
     {64, 128, 16, 2, 2, "f32_m64n128k16_w2x2"},
     {128, 128, 16, 2, 2, "f32_m128n128k16_w2x2"},
+    {128, 128, 16, 4, 2, "f32_m128n128k16_w4x2"},
+    {128, 128, 16, 2, 4, "f32_m128n128k16_w2x4"},
 };
 static const MixedConfig kBf16Configs[] = {
     {64, 64, 32, 2, 2, "bf16s_m64n64k32_w2x2"},
     {128, 64, 32, 2, 2, "bf16s_m128n64k32_w2x2"},
     {64, 128, 32, 2, 2, "bf16s_m64n128k32_w2x2"},
+    {128, 64, 32, 4, 2, "bf16s_m128n64k32_w4x2"},
+    {64, 128, 32, 2, 4, "bf16s_m64n128k32_w2x4"},
+    {128, 128, 32, 4, 2, "bf16s_m128n128k32_w4x2"},
+    {128, 128, 32, 2, 4, "bf16s_m128n128k32_w2x4"},
 };
 
 int mixed_config_count(int precision) {
@@ -612,6 +647,8 @@ hipError_t launch_contract_mixed(int precision, int config, int layout, const Co
       case 1: return launch_f32<128, 64, 16, 2, 2>(layout, p, s);
       case 2: return launch_f32<64, 128, 16, 2, 2>(layout, p, s);
       case 3: return launch_f32<128, 128, 16, 2, 2>(layout, p, s);
+      case 4: return launch_f32<128, 128, 16, 4, 2>(layout, p, s);
+      case 5: return launch_f32<128, 128, 16, 2, 4>(layout, p, s);
       default: return hipErrorInvalidValue;
     }
   }
@@ -620,6 +657,10 @@ hipError_t launch_contract_mixed(int precision, int config, int layout, const Co
     case 0: return al ? launch_bf<64, 64, 32, 2, 2, true>(layout, p, s) : launch_bf<64, 64, 32, 2, 2, false>(layout, p, s);
     case 1: return al ? launch_bf<128, 64, 32, 2, 2, true>(layout, p, s) : launch_bf<128, 64, 32, 2, 2, false>(layout, p, s);
     case 2: return al ? launch_bf<64, 128, 32, 2, 2, true>(layout, p, s) : launch_bf<64, 128, 32, 2, 2, false>(layout, p, s);
+    case 3: return al ? launch_bf<128, 64, 32, 4, 2, true>(layout, p, s) : launch_bf<128, 64, 32, 4, 2, false>(layout, p, s);
+    case 4: return al ? launch_bf<64, 128, 32, 2, 4, true>(layout, p, s) : launch_bf<64, 128, 32, 2, 4, false>(layout, p, s);
+    case 5: return al ? launch_bf<128, 128, 32, 4, 2, true>(layout, p, s) : launch_bf<128, 128, 32, 4, 2, false>(layout, p, s);
+    case 6: return al ? launch_bf<128, 128, 32, 2, 4, true>(layout, p, s) : launch_bf<128, 128, 32, 2, 4, false>(layout, p, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -46,8 +46,11 @@ def test_mixed_small(precision, term):
 
 
 @pytest.mark.parametrize("precision", list(TOL))
-def test_mixed_every_config_with_splits(precision):
-    prob = Problem(16, 48, 8, 16)
+@pytest.mark.parametrize("shape", [(16, 48, 8, 16), (22, 38, 11, 15)], ids=["planes", "packed"])
+def test_mixed_every_config_with_splits(precision, shape):
+    # every tile configuration (four and eight waves) with and without K splits, on K extents that
+    # are multiples of 8 (slice-plane layout for the split paths) and on ragged ones (packed)
+    prob = Problem(*shape)
     n = tm.Plan(*(lambda t: (t[0], "abij", t[1], "abcd", t[2], "cdij"))(
         [prob.gpu_tensor(None, "vvoo", fill=False), prob.gpu_tensor(None, "vvvv", fill=False),
          prob.gpu_tensor(None, "vvoo", fill=False)]), precision=precision).config_count()
