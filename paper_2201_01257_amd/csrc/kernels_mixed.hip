@@ -99,15 +99,86 @@ __device__ __forceinline__ int find_block(const PrepBlock* blocks, int n, int64_
   return lo;
 }
 
+// Planes layout, lanes along k: a wave converts kPrepUnroll consecutive (block, row, window)
+// items, 4 consecutive k of one row per lane and item.  The loads of all its items are issued
+// before any of them is converted, so each wave keeps kPrepUnroll windows of reads in flight.
+constexpr int kPrepUnroll = 4;
+
+__device__ __forceinline__ void prep_planes_kc(const PrepParams& P, int64_t first, int lane) {
+  static_assert(kSplitWindow == 4 * 64, "a wave converts one window, 4 k per lane");
+  typedef double d2_t __attribute__((ext_vector_type(2)));
+  const int32_t* __restrict__ pool = P.pool;
+  double x[kPrepUnroll][4];
+  int64_t pos[kPrepUnroll];
+  bool live[kPrepUnroll];
+#pragma unroll
+  for (int u = 0; u < kPrepUnroll; ++u) {
+    const int64_t item = first + u;
+    live[u] = false;
+    pos[u] = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[u][i] = 0.0;
+    if (item >= P.n_items) continue;  // wave-uniform
+    const PrepBlock pb = P.blocks[find_block(P.blocks, P.n_blocks, item)];
+    const int64_t local = item - pb.item0;
+    const int k0 = (int)(local % pb.nwin) * kSplitWindow, row = (int)(local / pb.nwin);
+    const int k = k0 + 4 * lane;
+    const int k1 = min(pb.kext, k0 + kSplitWindow);
+    pos[u] = pb.off + (int64_t)row * pb.kext + k;
+    live[u] = k < k1;  // k1 is a multiple of 8: all four k are inside or all outside
+    if (!live[u]) continue;
+    const int64_t rowoff = pb.off + pool[pb.tab_row + row];
+    int32_t t[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t[i] = pool[pb.tab_k + k + i];
+    const int64_t a = rowoff + t[0];
+    if (t[1] == t[0] + 1 && t[2] == t[0] + 2 && t[3] == t[0] + 3 && (a & 1) == 0) {
+      // four consecutive elements at a 16-byte boundary: two 16-byte loads
+      const d2_t lo = *reinterpret_cast<const d2_t*>(P.x + a), hi = *reinterpret_cast<const d2_t*>(P.x + a + 2);
+      x[u][0] = lo[0];
+      x[u][1] = lo[1];
+      x[u][2] = hi[0];
+      x[u][3] = hi[1];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[u][i] = P.x[rowoff + t[i]];
+    }
+  }
+  const int ns = P.aligned ? 4 : 3;
+  unsigned short* __restrict__ out = static_cast<unsigned short*>(P.out);
+#pragma unroll
+  for (int u = 0; u < kPrepUnroll; ++u) {
+    if (first + u >= P.n_items) break;  // wave-uniform
+    double mx = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) mx = fmax(mx, fabs(x[u][i]));
+    const int e = window_exponent(wave_max(mx));
+    if (!live[u]) continue;
+    uint64_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = P.aligned ? split_aligned(x[u][i], e) : split_plain(x[u][i]);
+    for (int sl = 0; sl < ns; ++sl) {
+      uint64_t v = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v |= ((w[i] >> (16 * sl)) & 0xFFFFull) << (16 * i);
+      *reinterpret_cast<uint64_t*>(out + sl * P.plane_stride + pos[u]) = v;
+    }
+  }
+}
+
 // One wave per item.  ROWS_ALONG_LANES = false: the operand's stride-1 label is summed, so an item
 // is one (block, row, window) and the lanes run along k (coalesced); the window maximum is a wave
 // reduction.  ROWS_ALONG_LANES = true: an item is (block, 64 rows, window), each lane owns a row
 // and walks the window (lanes coalesce along the row label).
 template <bool ROWS_ALONG_LANES>
 __global__ __launch_bounds__(256) void k_prep_split(PrepParams P) {
+  const int lane = threadIdx.x & 63;
+  if (!ROWS_ALONG_LANES && P.planes) {
+    prep_planes_kc(P, ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kPrepUnroll, lane);
+    return;
+  }
   const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (item >= P.n_items) return;
-  const int lane = threadIdx.x & 63;
   const int b = find_block(P.blocks, P.n_blocks, item);
   const PrepBlock pb = P.blocks[b];
   const int64_t local = item - pb.item0;
@@ -121,47 +192,7 @@ __global__ __launch_bounds__(256) void k_prep_split(PrepParams P) {
     // (lanes along rows) consecutive k of one row and writes each slice plane's part at once
     const int ns = P.aligned ? 4 : 3;
     unsigned short* __restrict__ out = static_cast<unsigned short*>(P.out);
-    if (!ROWS_ALONG_LANES) {
-      const int row = rg;
-      const int64_t rowoff = pb.off + pool[pb.tab_row + row];
-      static_assert(kSplitWindow == 4 * 64, "a wave converts one window, 4 k per lane");
-      const int k = k0 + 4 * lane;
-      double x[4] = {0.0, 0.0, 0.0, 0.0};
-      if (k < k1) {
-        int32_t t[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) t[i] = pool[pb.tab_k + k + i];
-        const int64_t a = rowoff + t[0];
-        if (t[1] == t[0] + 1 && t[2] == t[0] + 2 && t[3] == t[0] + 3 && (a & 1) == 0) {
-          // four consecutive elements at a 16-byte boundary: two 16-byte loads
-          typedef double d2_t __attribute__((ext_vector_type(2)));
-          const d2_t lo = *reinterpret_cast<const d2_t*>(P.x + a), hi = *reinterpret_cast<const d2_t*>(P.x + a + 2);
-          x[0] = lo[0];
-          x[1] = lo[1];
-          x[2] = hi[0];
-          x[3] = hi[1];
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) x[i] = P.x[rowoff + t[i]];
-        }
-      }
-      double mx = 0.0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) mx = fmax(mx, fabs(x[i]));
-      const int e = window_exponent(wave_max(mx));
-      if (k < k1) {
-        uint64_t w[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) w[i] = P.aligned ? split_aligned(x[i], e) : split_plain(x[i]);
-        const int64_t pos = pb.off + (int64_t)row * pb.kext + k;
-        for (int sl = 0; sl < ns; ++sl) {
-          uint64_t v = 0;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) v |= ((w[i] >> (16 * sl)) & 0xFFFFull) << (16 * i);
-          *reinterpret_cast<uint64_t*>(out + sl * P.plane_stride + pos) = v;
-        }
-      }
-    } else {
+    {  // lanes along rows (lanes along k: prep_planes_kc)
       const int row = rg * 64 + lane;
       if (row >= pb.rows) return;
       const int64_t rowoff = pb.off + pool[pb.tab_row + row];
@@ -224,7 +255,8 @@ __global__ __launch_bounds__(256) void k_prep_split(PrepParams P) {
 
 hipError_t launch_prep_split(const PrepParams& p, bool rows_along_lanes, hipStream_t s) {
   if (p.n_items <= 0) return hipSuccess;
-  const dim3 g((unsigned)((p.n_items + 3) / 4)), b(256);
+  const int64_t per_block = (!rows_along_lanes && p.planes) ? 4 * kPrepUnroll : 4;  // items per workgroup
+  const dim3 g((unsigned)((p.n_items + per_block - 1) / per_block)), b(256);
   if (rows_along_lanes) hipLaunchKernelGGL(k_prep_split<true>, g, b, 0, s, p);
   else hipLaunchKernelGGL(k_prep_split<false>, g, b, 0, s, p);
   return hipGetLastError();
