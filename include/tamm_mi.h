@@ -65,8 +65,11 @@ typedef enum {
  *            residual is split into three bfloat16 terms; the ten products of term order
  *            i + j <= 3.  Lead*lead products of one window sum exactly in float32 (kept in their
  *            own accumulator); only the residual products see float32 rounding.
- * The split precisions first write the split operands into the plan workspace (one packed
- * 64-bit word per element); their workspace is correspondingly larger. */
+ * The split precisions first write the split operands into the plan workspace, as bfloat16
+ * slice planes (slice s of every element in plane s, each block stored [row][k] over its
+ * flattened row and K labels) when every operand block's flattened K extent is a multiple of 8,
+ * otherwise as one packed 64-bit word of slices per element at the float64 element offsets
+ * (tamm_plan_stats.gather_layout bit 3 tells which); their workspace is correspondingly larger. */
 typedef enum { TAMM_PREC_F64 = 0, TAMM_PREC_F32 = 1, TAMM_PREC_BF16X3 = 2, TAMM_PREC_BF16X4_ALIGNED = 3 } tamm_precision;
 
 /* User non-zero check (Sec. III-A: a user-defined non-zero check used both for allocation and

@@ -5,9 +5,10 @@
 //   float32 (v_mfma_f32_16x16x4_f32): operands rounded to float32 (round to nearest even) while
 //       they are gathered into LDS.
 //   split bfloat16 (v_mfma_f32_16x16x32_bf16): each operand is first split by k_prep_split into
-//       bfloat16 slices stored as one packed 64-bit word per element (slice s in bits 16s..16s+15),
-//       at the same element offsets as the float64 operand; the contraction then multiplies
-//       selected slice pairs.
+//       bfloat16 slices, stored either as slice planes (plane s holds slice s of every element,
+//       each block [row][k]; used when every block's K extent is a multiple of 8) or as one packed
+//       64-bit word per element (slice s in bits 16s..16s+15) at the float64 element offsets; the
+//       contraction then multiplies selected slice pairs.
 //         - three plain slices (x ~ b0 + b1 + b2, b_i = bf16(x - b_0 - ... - b_{i-1})), the six
 //           products b_i*b_j with i + j <= 2, one float32 accumulator per window;
 //         - aligned lead: slice 0 is x rounded to a fixed-point grid of 8 bits below the maximum
