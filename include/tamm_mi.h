@@ -65,6 +65,11 @@ typedef enum {
  *            residual is split into three bfloat16 terms; the ten products of term order
  *            i + j <= 3.  Lead*lead products of one window sum exactly in float32 (kept in their
  *            own accumulator); only the residual products see float32 rounding.
+ * The flattened summed indices of an operand block run over the summed labels in the dimension
+ * order of the operand that does not hold out's last label, unless only the other operand has a
+ * summed label as its last dimension (then in that operand's order); the last label varies
+ * fastest.  Windows are consecutive 256-long runs of them within each (block, row), where a row
+ * is one value of the operand's remaining (output) labels.
  * The split precisions first write the split operands into the plan workspace, as bfloat16
  * slice planes (slice s of every element in plane s, each block stored [row][k] over its
  * flattened row and K labels) when every operand block's flattened K extent is a multiple of 8,
@@ -235,6 +240,16 @@ int tamm_plan_contract(tamm_plan* p, double alpha, double beta, void* stream);
  * K tile-tuple index of every surviving pair (out block major, pairs in lexicographic order,
  * sum(counts) entries).  For tests and statistics. */
 int tamm_plan_screen_result(tamm_plan* p, void* stream, int32_t* counts, int32_t* k_tuple_idx);
+
+/* The operand split of a split-bfloat16 plan (BF16X3 or BF16X4_ALIGNED) exactly as its
+ * contraction multiplies it.  For operand `which` (0 = lhs, 1 = rhs): one 64-bit word per stored
+ * element, at the element's offset in that tensor's storage, holding slice s as bfloat16 bits in
+ * bits 16s..16s+15 (three slices: bits 48..63 zero).  The windows of the aligned lead slice are
+ * those described at tamm_precision.  `out_dev`: caller-owned device memory of at least 8 bytes
+ * per stored element of the operand.  Enqueued on stream.  ERR_UNSUPPORTED for F64 and F32 plans,
+ * ERR_UNBOUND without a bound workspace or tensor storage, ERR_WORKSPACE if `bytes` is too small.
+ * For tests of the split (its values have an exact definition) and for inspecting it. */
+int tamm_plan_split_operand(const tamm_plan* p, int32_t which, void* out_dev, size_t bytes, void* stream);
 
 int tamm_plan_destroy(tamm_plan* p);
 

@@ -24,8 +24,9 @@ Readings taken where the paper is silent are listed in the module docstrings the
 Pins: every function here is checked by the ``-m "not gpu"`` tests against something other
 than itself (dense brute force, a BLAS GEMM special case, the Eq. (cc9)-(cc11) identity,
 closed-form block counts, the worked tiling example of Fig. 1, invariants, finite
-differences).  The mixed-precision error model has no exact pin (parity unpinned beyond the
-tolerance it states).
+differences).  The operand splits of the mixed-precision paths (``oracle.split``) are pinned
+by their own tests; the error of their float32 accumulation has no exact pin (parity unpinned
+beyond the tolerance each precision states).
 """
 
 from .tiling import Space, spin_conserving

@@ -316,6 +316,16 @@ class Plan:
             res.append(lst)
         return res
 
+    def split_operand(self, which: int, stream=None):
+        """The split-bfloat16 slices of operand `which` (0 = lhs, 1 = rhs) as the contraction uses
+        them: one int64 word per stored element at the operand's element offsets, slice s in bits
+        16s..16s+15 (see tamm_plan_split_operand)."""
+        t = self.lhs if which == 0 else self.rhs
+        out = _torch().empty(max(t.numel, 1), dtype=_torch().int64, device=t.data.device)
+        s = current_stream_handle() if stream is None else stream
+        check(load().tamm_plan_split_operand(self._h, which, ctypes.c_void_p(out.data_ptr()), out.numel() * 8, s))
+        return out[:t.numel]
+
     def __del__(self, _d=_destroy):
         _d(self, "tamm_plan_destroy")
 

@@ -871,6 +871,29 @@ extern "C" int tamm_plan_screen_result(tamm_plan* p, void* stream, int32_t* coun
   return ok();
 }
 
+extern "C" int tamm_plan_split_operand(const tamm_plan* p, int32_t which, void* out_dev, size_t bytes, void* stream) {
+  if (!p || !out_dev || (which != 0 && which != 1)) return fail(TAMM_ERR_ARG, "null plan or buffer, or operand not 0 or 1");
+  if (p->prec != TAMM_PREC_BF16X3 && p->prec != TAMM_PREC_BF16X4_ALIGNED)
+    return fail(TAMM_ERR_UNSUPPORTED, "the plan's precision splits no operand");
+  const int rc = check_bound(p);
+  if (rc != TAMM_OK) return rc;
+  const bool is_a = (which == 0) != p->swapped;  // lhs is A unless it holds out's last label
+  const tamm_tensor* t = is_a ? p->A : p->B;
+  if (bytes < (size_t)t->numel * sizeof(uint64_t))
+    return fail(TAMM_ERR_WORKSPACE, "output buffer of %zu bytes is smaller than %lld words", bytes, (long long)t->numel);
+  PrepParams pa{};
+  pa.x = t->dev;
+  pa.out = out_dev;
+  pa.blocks = (const PrepBlock*)(p->ws + (is_a ? p->off_prepA : p->off_prepB));
+  pa.pool = (const int32_t*)(p->ws + p->lay.pool);
+  pa.n_items = is_a ? p->prepA_items : p->prepB_items;
+  pa.n_blocks = (int32_t)(is_a ? p->prepA.size() : p->prepB.size());
+  pa.aligned = p->prec == TAMM_PREC_BF16X4_ALIGNED ? 1 : 0;
+  pa.planes = 0;  // packed words at the float64 element offsets
+  HIP_TRY(launch_prep_split(pa, is_a ? !p->a_kc : !p->b_kc, (hipStream_t)stream));
+  return ok();
+}
+
 extern "C" int tamm_plan_destroy(tamm_plan* p) {
   delete p;
   return ok();

@@ -5,6 +5,10 @@ Tolerances are the stated error budgets of each scheme (no exact pin exists for 
   bf16x3 (three plain bfloat16 slices, six products):                               <= 3e-7
   f32 (float32 operands and window sums):                                           <= 1e-6
 Every path promotes float32 window sums to float64 and runs a float64 epilogue.
+
+The operand splits themselves have an exact definition: the words the library multiplies
+(tamm_plan_split_operand) are compared bit for bit with the oracle's split (oracle/split.py) of
+the same seeded operands, for both split layouts and both operand gather modes.
 """
 
 import numpy as np
@@ -14,6 +18,7 @@ import torch
 import oracle
 from paper_2201_01257_amd import core as tm
 from paper_2201_01257_amd import synth
+from oracle import split as osplit
 from tests.gpu_util import Problem, max_rel
 
 pytestmark = pytest.mark.gpu
@@ -79,3 +84,36 @@ def test_aligned_split_windows_longer_than_one():
     got, ref, _ = run(prob, "ladder", "bf16x4_aligned")
     rel, _ = max_rel(got, ref)
     assert rel <= TOL["bf16x4_aligned"], rel
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16x4_aligned"])
+@pytest.mark.parametrize("shape", [(24, 40, 12, 16), (22, 38, 11, 15)], ids=["planes", "packed"])
+@pytest.mark.parametrize("term", ["ladder", "ring", "hh_int", "t1_o"])
+def test_operand_split_matches_oracle_bitwise(precision, shape, term):
+    # the split slices have an exact definition: every word of both operands, bit for bit
+    prob = Problem(*shape)
+    (on, op, ol), (ln, lp, ll), (rn, rp, rl), _ = synth.TERMS[term]
+    L, R, O = prob.gpu_tensor(ln, lp), prob.gpu_tensor(rn, rp), prob.gpu_tensor(on, op, fill=False)
+    plan = tm.Plan(O, ol, L, ll, R, rl, precision=precision)
+    k_order = osplit.summed_label_order(ol, ll, rl)
+    for which, (t, name, pattern, lbl) in enumerate([(L, ln, lp, ll), (R, rn, rp, rl)]):
+        words = plan.split_operand(which)
+        torch.cuda.synchronize()
+        words = words.cpu().numpy().view(np.uint64)
+        ot = prob.oracle_tensor(name, pattern)
+        for b in range(t.nblocks):
+            tile = tuple(int(x) for x in t.block_tiles[b])
+            _, ext = t.block_lo_ext(b)
+            off = int(t.block_off[b])
+            got = words[off:off + int(np.prod(ext))].reshape(ext)
+            ref = osplit.split_block(ot.blocks[tile], lbl, k_order, aligned=precision == "bf16x4_aligned")
+            assert np.array_equal(got, ref), (precision, term, which, tile)
+
+
+def test_split_operand_rejects_float64_plans():
+    prob = Problem(16, 48, 8, 16)
+    (on, op, ol), (ln, lp, ll), (rn, rp, rl), _ = synth.TERMS["ladder"]
+    plan = tm.Plan(prob.gpu_tensor(on, op, fill=False), ol, prob.gpu_tensor(ln, lp, fill=False), ll,
+                   prob.gpu_tensor(rn, rp, fill=False), rl)
+    with pytest.raises(tm.TammError):
+        plan.split_operand(0)
