@@ -12,7 +12,7 @@ struct tamm_denominator {
   tamm_tensor* out = nullptr;
   const tamm_tensor* in = nullptr;
   int8_t sign[kMaxRank] = {0};
-  int32_t chunk = 4096;
+  int32_t chunk = 1024;  // elements per workgroup: one batch of 4 per thread
   std::vector<int32_t> item_block, item_start;
   size_t off_boff = 0, off_btiles = 0, off_toff = 0, off_tsz = 0, off_iblock = 0, off_istart = 0, ws_size = 0;
   char* ws = nullptr;

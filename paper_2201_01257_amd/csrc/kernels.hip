@@ -346,8 +346,12 @@ hipError_t launch_contract_f64(int config, int layout, const ContractParams& p, 
 // stored block; IEEE float64 division; the denominator is summed in the documented order (the
 // energies of the +1 dimensions in dimension order, then minus those of the -1 dimensions).
 // A thread splits its first element into per-dimension indices once and then steps by the
-// workgroup size with a mixed-radix add, so no integer division runs per element.
+// workgroup size with a mixed-radix add, so no integer division runs per element.  Elements go in
+// batches of kDenomUnroll per thread whose loads are all issued before any division, so each wave
+// keeps that many coalesced loads in flight.
 // ---------------------------------------------------------------------------------------------
+constexpr int kDenomUnroll = 4;
+
 template <int RANK>
 __device__ __forceinline__ void denominator_block(const DenomParams& P, int b, int e0, int e1) {
   int lo[RANK], ext[RANK], idx[RANK], step[RANK];
@@ -365,31 +369,37 @@ __device__ __forceinline__ void denominator_block(const DenomParams& P, int b, i
     step[d] = srem % ext[d];
     srem /= ext[d];
   }
-  const int64_t base = P.block_off[b];
-  for (int e = e0 + (int)threadIdx.x; e < e1; e += (int)blockDim.x) {
-    double den = 0.0;
-    bool first = true;
+  const double* __restrict__ in = P.in + P.block_off[b];
+  double* __restrict__ out = P.out + P.block_off[b];
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += kDenomUnroll * (int)blockDim.x) {
+    // all loads of the batch first (the element and its energies), then the arithmetic: no
+    // load waits behind another's use
+    double x[kDenomUnroll], ev[kDenomUnroll][RANK];
 #pragma unroll
-    for (int d = 0; d < RANK; ++d)
-      if (P.sign[d] > 0) {
-        const double v = P.energy[d][lo[d] + idx[d]];
-        den = first ? v : den + v;
-        first = false;
+    for (int u = 0; u < kDenomUnroll; ++u) {
+      const int eu = e + u * (int)blockDim.x;
+      x[u] = eu < e1 ? in[eu] : 1.0;
+#pragma unroll
+      for (int d = 0; d < RANK; ++d) ev[u][d] = P.sign[d] != 0 ? P.energy[d][lo[d] + idx[d]] : 0.0;
+      int carry = 0;  // idx += step in the block's mixed radix (each digit stays below 2*ext)
+#pragma unroll
+      for (int d = RANK - 1; d >= 0; --d) {
+        idx[d] += step[d] + carry;
+        carry = idx[d] >= ext[d] ? 1 : 0;
+        idx[d] -= carry ? ext[d] : 0;
       }
+    }
 #pragma unroll
-    for (int d = 0; d < RANK; ++d)
-      if (P.sign[d] < 0) {
-        const double v = P.energy[d][lo[d] + idx[d]];
-        den = first ? -v : den - v;
-        first = false;
-      }
-    P.out[base + e] = P.in[base + e] / den;
-    int carry = 0;  // idx += step in the block's mixed radix (each digit stays below 2*ext)
+    for (int u = 0; u < kDenomUnroll; ++u) {
+      double den = 0.0;  // 0 + v and 0 - v are exact: the first term enters unchanged
 #pragma unroll
-    for (int d = RANK - 1; d >= 0; --d) {
-      idx[d] += step[d] + carry;
-      carry = idx[d] >= ext[d] ? 1 : 0;
-      idx[d] -= carry ? ext[d] : 0;
+      for (int d = 0; d < RANK; ++d)
+        if (P.sign[d] > 0) den += ev[u][d];
+#pragma unroll
+      for (int d = 0; d < RANK; ++d)
+        if (P.sign[d] < 0) den -= ev[u][d];
+      const int eu = e + u * (int)blockDim.x;
+      if (eu < e1) out[eu] = x[u] / den;
     }
   }
 }
