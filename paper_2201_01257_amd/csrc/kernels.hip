@@ -193,24 +193,38 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
             part[m * NT + n] = acc[i][j][r];
           }
     } else {
+      // through out's offset tables: every table entry first (the tables are padded, so rows and
+      // columns past the block read in bounds), then per row block the old values (beta != 0),
+      // then the results, so that no load waits behind the use of another
       const double alpha = pr.alpha, beta = pr.beta;
-      double* __restrict__ Cg = pr.C;
+      __attribute__((address_space(1))) double* __restrict__ Cg = (__attribute__((address_space(1))) double*)pr.C;
+      const int mb = w.m0 + wm * WM + lq, nb = w.n0 + wn * WN + lr;
+      int32_t rt[FM][4], ct[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = w.m0 + wm * WM + i * 16 + 4 * r + lq;
-          if (m >= blk.mext) continue;
-          const int64_t rowoff = blk.c_off + gload(pool + blk.c_tabM + m);
+        for (int r = 0; r < 4; ++r) rt[i][r] = gload(pool + blk.c_tabM + mb + i * 16 + 4 * r);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) ct[j] = gload(pool + blk.c_tabN + nb + j * 16);
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        double old[4][FN];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
           for (int j = 0; j < FN; ++j) {
-            const int n = w.n0 + wn * WN + j * 16 + lr;
-            if (n >= blk.next) continue;
-            const int64_t idx = rowoff + gload(pool + blk.c_tabN + n);
-            const double v = alpha * acc[i][j][r];
-            Cg[idx] = (beta == 0.0) ? v : beta * Cg[idx] + v;
+            const bool live = mb + i * 16 + 4 * r < blk.mext && nb + j * 16 < blk.next;
+            old[r][j] = (beta != 0.0 && live) ? Cg[blk.c_off + rt[i][r] + ct[j]] : 0.0;
           }
-        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            const bool live = mb + i * 16 + 4 * r < blk.mext && nb + j * 16 < blk.next;
+            const double v = alpha * acc[i][j][r];
+            if (live) Cg[blk.c_off + rt[i][r] + ct[j]] = (beta == 0.0) ? v : beta * old[r][j] + v;
+          }
+      }
     }
     if (!P.next_item) break;
     __syncthreads();  // s_next is free
@@ -229,7 +243,11 @@ hipError_t launch_set_counter(int32_t* counter, int32_t value, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Ordered reduction of K-split partial tiles (split 0, 1, ... in order) and the epilogue.
+// Ordered reduction of K-split partial tiles (split 0, 1, ... in order) and the epilogue.  A
+// thread takes kReduceUnroll elements at a time and issues all their loads (table entries, then
+// the partials and old values) before any use.
+constexpr int kReduceUnroll = 4;
+
 __global__ __launch_bounds__(256) void k_reduce(ReduceParams P) {
   const int t = blockIdx.x;
   if (t >= P.n_items) return;
@@ -238,14 +256,36 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceParams P) {
   const OutBlockDesc blk = pr.blocks[it.ob];
   const int tile = P.tile_m * P.tile_n;
   const double* part = pr.partial + (int64_t)it.tile * tile;
-  for (int e = threadIdx.x; e < tile; e += blockDim.x) {
-    const int m = it.m0 + e / P.tile_n, n = it.n0 + e % P.tile_n;
-    if (m >= blk.mext || n >= blk.next) continue;
-    double s = 0.0;
-    for (int k = 0; k < it.nsplit; ++k) s += part[(int64_t)k * tile + e];
-    const int64_t idx = blk.c_off + pr.pool[blk.c_tabM + m] + pr.pool[blk.c_tabN + n];
-    const double v = pr.alpha * s;
-    pr.C[idx] = (pr.beta == 0.0) ? v : pr.beta * pr.C[idx] + v;
+  const double alpha = pr.alpha, beta = pr.beta;
+  __attribute__((address_space(1))) double* __restrict__ Cg = (__attribute__((address_space(1))) double*)pr.C;
+  for (int e0 = threadIdx.x; e0 < tile; e0 += kReduceUnroll * blockDim.x) {
+    int64_t idx[kReduceUnroll];
+    bool live[kReduceUnroll];
+#pragma unroll
+    for (int u = 0; u < kReduceUnroll; ++u) {
+      const int e = e0 + u * blockDim.x;
+      const int m = it.m0 + e / P.tile_n, n = it.n0 + e % P.tile_n;
+      live[u] = e < tile && m < blk.mext && n < blk.next;
+      idx[u] = live[u] ? blk.c_off + pr.pool[blk.c_tabM + m] + pr.pool[blk.c_tabN + n] : 0;
+    }
+    double s[kReduceUnroll], old[kReduceUnroll];
+#pragma unroll
+    for (int u = 0; u < kReduceUnroll; ++u) {
+      old[u] = (beta != 0.0 && live[u]) ? Cg[idx[u]] : 0.0;
+      s[u] = 0.0;
+    }
+    for (int k = 0; k < it.nsplit; ++k) {  // split order; the elements' loads of one split together
+#pragma unroll
+      for (int u = 0; u < kReduceUnroll; ++u) {
+        const int e = e0 + u * blockDim.x;
+        s[u] += live[u] ? part[(int64_t)k * tile + e] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kReduceUnroll; ++u) {
+      const double v = alpha * s[u];
+      if (live[u]) Cg[idx[u]] = (beta == 0.0) ? v : beta * old[u] + v;
+    }
   }
 }
 

@@ -278,24 +278,39 @@ __device__ __forceinline__ void epilogue_f32layout(const ProblemDesc& pr, const 
         for (int r = 0; r < 4; ++r) part[(wm * WM + i * 16 + 4 * lq + r) * NT + wn * WN + j * 16 + lr] = acc[i][j][r];
     return;
   }
+  // through out's offset tables: every table entry first (the tables are padded, so rows and
+  // columns past the block read in bounds), then per row block the old values (beta != 0), then
+  // the results, so that no load waits behind the use of another
   const double alpha = pr.alpha, beta = pr.beta;
   const int32_t* pool = pr.pool;
+  __attribute__((address_space(1))) double* __restrict__ Cg = (__attribute__((address_space(1))) double*)pr.C;
+  const int mb = w.m0 + wm * WM + 4 * lq, nb = w.n0 + wn * WN + lr;
+  int32_t rt[FM][4], ct[FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = w.m0 + wm * WM + i * 16 + 4 * lq + r;
-      if (m >= blk.mext) continue;
-      const int64_t rowoff = blk.c_off + pool[blk.c_tabM + m];
+    for (int r = 0; r < 4; ++r) rt[i][r] = pool[blk.c_tabM + mb + i * 16 + r];
+#pragma unroll
+  for (int j = 0; j < FN; ++j) ct[j] = pool[blk.c_tabN + nb + j * 16];
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    double old[4][FN];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        const int n = w.n0 + wn * WN + j * 16 + lr;
-        if (n >= blk.next) continue;
-        const int64_t idx = rowoff + pool[blk.c_tabN + n];
-        const double v = alpha * acc[i][j][r];
-        pr.C[idx] = (beta == 0.0) ? v : beta * pr.C[idx] + v;
+        const bool live = mb + i * 16 + r < blk.mext && nb + j * 16 < blk.next;
+        old[r][j] = (beta != 0.0 && live) ? Cg[blk.c_off + rt[i][r] + ct[j]] : 0.0;
       }
-    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const bool live = mb + i * 16 + r < blk.mext && nb + j * 16 < blk.next;
+        const double v = alpha * acc[i][j][r];
+        if (live) Cg[blk.c_off + rt[i][r] + ct[j]] = (beta == 0.0) ? v : beta * old[r][j] + v;
+      }
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
