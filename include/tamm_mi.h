@@ -261,16 +261,19 @@ int tamm_plan_destroy(tamm_plan* p);
  * write storage that another member reads or writes (checked at execution, ERR_ARG).  Plans and
  * their tensors must outlive the group; the group uses its own workspace (the members' own
  * workspaces are not needed).  The group ignores the members' kernel configurations and runs
- * without K splits.
+ * without K splits.  Members are grouped into classes by their gather layout (operand
+ * orientations and 8- or 16-byte gathers, see tamm_plan_stats.gather_layout); each class has its
+ * own persistent launch, kernel configuration (tile shape) and grid.
  * ------------------------------------------------------------------------------------------ */
 int tamm_group_create(tamm_plan* const* plans, int32_t n, tamm_group** g);
 int tamm_group_workspace_size(const tamm_group* g, size_t* bytes);
 /* Bind caller-owned device workspace (256-byte aligned) and upload the members' static tables
  * (synchronous).  Drops a captured graph. */
 int tamm_group_bind_workspace(tamm_group* g, void* dev_ptr, size_t bytes);
-/* Select the kernel configuration (-1 = default) and the persistent grid size (0 = every
- * resident slot: compute units x workgroups of the configuration that fit on one).  Requires
- * re-querying the workspace size and re-binding. */
+/* Select one kernel configuration for every class (-1 = each class's default: the least padding)
+ * and the persistent grid size (0 = every resident slot: compute units x workgroups of the
+ * configuration that fit on one).  Requires re-binding (the workspace size does not depend on
+ * the configuration). */
 int tamm_group_set_config(tamm_group* g, int32_t config, int32_t grid);
 /* alpha and beta are host arrays of n values, read during the call.  If a graph was captured
  * with the same alpha/beta and the members' storage bindings are unchanged, the graph is
@@ -284,14 +287,14 @@ int tamm_group_execute(tamm_group* g, const double* alpha, const double* beta, v
  * copy nodes) into a hipGraph on an internal stream, with alpha/beta fixed at these values;
  * later tamm_group_execute calls with the same values replay it on their stream. */
 int tamm_group_capture(tamm_group* g, const double* alpha, const double* beta, void* stream);
-/* Autotuner for groups: every kernel configuration with persistent grids of 1, 2 and 4
- * workgroups per compute unit and the occupancy-sized grid, timed on stream with alpha = 0,
- * beta = 1; keeps the fastest and caches it in cache_path (if non-empty) under the group's
- * structural signature.  Needs a
- * bound workspace large enough for the candidates (candidates that do not fit are skipped).
+/* Autotuner for groups: for every class separately, every kernel configuration with persistent
+ * grids of 1, 2 and 4 workgroups per compute unit and the occupancy-sized grid, the class's launch
+ * timed on stream with alpha = 0, beta = 1; keeps each class's fastest and caches them in
+ * cache_path (if non-empty) under the group's structural signature.  Needs a bound workspace.
  * Synchronises the stream. */
 int tamm_group_autotune(tamm_group* g, void* stream, const char* cache_path, int32_t reps);
-/* Active configuration, persistent grid (0 = automatic) and number of work items. */
+/* Configuration and persistent grid (0 = automatic) of the class with the most work items, and
+ * the number of work items of all classes. */
 int tamm_group_stats(const tamm_group* g, int32_t* config, int32_t* grid, int64_t* work_items);
 int tamm_group_destroy(tamm_group* g);
 

@@ -1010,9 +1010,10 @@ struct tamm_group {
   size_t off_sdesc = 0, off_pdesc = 0, off_sitems = 0, off_work = 0, off_counter = 0, ws_size = 0;
   std::vector<int32_t> sitem_prob, sitem_block;
   std::vector<WorkItem> work;       // grouped by gather layout class, each class longest first
+  size_t work_capacity = 0;         // work items of the largest mix of per-class configurations
   int32_t cls_begin[kLayouts + 1] = {};  // work range of gather layout c: [cls_begin[c], cls_begin[c+1])
-  int config = -1;
-  int grid = 0;   // 0: automatic
+  int cfg[kLayouts] = {};   // kernel configuration of each layout class (its tile shape)
+  int grid[kLayouts] = {};  // persistent grid of each layout class (0: automatic)
   uint64_t signature = 0;
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -1030,53 +1031,64 @@ static void group_drop_graph(tamm_group* g) {
   g->graph = nullptr;
 }
 
-static int group_configure(tamm_group* g, int config) {
-  if (config < 0) {
-    // the configuration with the least padding over all members, ties to the larger tile
-    double best = 1e30;
-    for (int c = 0; c < f64_config_count(); ++c) {
-      const F64Config& f = f64_config(c);
-      if (f.kt != 16 || f.wgm * f.wgn != 4 || f.mt > 128 || f.nt > 128) continue;
-      double area = 0, useful = 0;
-      for (auto* p : g->plans)
-        for (const auto& b : p->blocks) {
-          area += (double)((b.mext + f.mt - 1) / f.mt) * f.mt * ((b.next + f.nt - 1) / f.nt) * f.nt;
-          useful += (double)b.mext * b.next;
-        }
-      const double score = (useful > 0 ? area / useful : 1.0) - 1e-6 * f.mt * f.nt;
-      if (score < best) {
-        best = score;
-        config = c;
+// Default configuration of a set of members: the one with the least padding, ties to the larger
+// tile.
+static int group_default_config(const tamm_group* g, int layout) {
+  int config = 0;
+  double best = 1e30;
+  for (int c = 0; c < f64_config_count(); ++c) {
+    const F64Config& f = f64_config(c);
+    if (f.kt != 16 || f.wgm * f.wgn != 4 || f.mt > 128 || f.nt > 128) continue;
+    double area = 0, useful = 0;
+    for (auto* p : g->plans) {
+      if (layout >= 0 && gather_layout(p) != layout) continue;
+      for (const auto& b : p->blocks) {
+        area += (double)((b.mext + f.mt - 1) / f.mt) * f.mt * ((b.next + f.nt - 1) / f.nt) * f.nt;
+        useful += (double)b.mext * b.next;
       }
     }
+    const double score = (useful > 0 ? area / useful : 1.0) - 1e-6 * f.mt * f.nt;
+    if (score < best) {
+      best = score;
+      config = c;
+    }
   }
-  if (config < 0 || config >= f64_config_count()) return fail(TAMM_ERR_ARG, "configuration %d does not exist", config);
-  const F64Config& f = f64_config(config);
+  return config;
+}
+
+// Work lists of every layout class with the class's configuration cfgs[c] (< 0: the class's
+// default), each heaviest first.
+static int group_configure_classes(tamm_group* g, const int* cfgs) {
+  for (int c = 0; c < kLayouts; ++c) {
+    const int k = cfgs[c] < 0 ? group_default_config(g, c) : cfgs[c];
+    if (k >= f64_config_count()) return fail(TAMM_ERR_ARG, "configuration %d does not exist", k);
+    g->cfg[c] = k;
+  }
   struct Tile {
     double cost;
     WorkItem w;
   };
-  std::vector<Tile> tiles;
-  for (size_t q = 0; q < g->plans.size(); ++q) {
-    const tamm_plan* p = g->plans[q];
-    int32_t t = 0;
-    for (size_t b = 0; b < p->blocks.size(); ++b) {
-      const auto& d = p->blocks[b];
-      for (int32_t m0 = 0; m0 < d.mext; m0 += f.mt)
-        for (int32_t n0 = 0; n0 < d.next; n0 += f.nt)
-          tiles.push_back(Tile{p->block_cost[b] * std::min(f.mt, d.mext - m0) * std::min(f.nt, d.next - n0),
-                               WorkItem{(int32_t)q, (int32_t)b, m0, n0, 0, t++}});
-    }
-  }
-  std::stable_sort(tiles.begin(), tiles.end(), [](const Tile& x, const Tile& y) { return x.cost > y.cost; });
   g->work.clear();
   for (int c = 0; c < kLayouts; ++c) {
+    const F64Config& f = f64_config(g->cfg[c]);
+    std::vector<Tile> tiles;
+    for (size_t q = 0; q < g->plans.size(); ++q) {
+      const tamm_plan* p = g->plans[q];
+      if (gather_layout(p) != c) continue;
+      int32_t t = 0;
+      for (size_t b = 0; b < p->blocks.size(); ++b) {
+        const auto& d = p->blocks[b];
+        for (int32_t m0 = 0; m0 < d.mext; m0 += f.mt)
+          for (int32_t n0 = 0; n0 < d.next; n0 += f.nt)
+            tiles.push_back(Tile{p->block_cost[b] * std::min(f.mt, d.mext - m0) * std::min(f.nt, d.next - n0),
+                                 WorkItem{(int32_t)q, (int32_t)b, m0, n0, 0, t++}});
+      }
+    }
+    std::stable_sort(tiles.begin(), tiles.end(), [](const Tile& x, const Tile& y) { return x.cost > y.cost; });
     g->cls_begin[c] = (int32_t)g->work.size();
-    for (auto& t : tiles)
-      if (gather_layout(g->plans[t.w.prob]) == c) g->work.push_back(t.w);
+    for (auto& t : tiles) g->work.push_back(t.w);
   }
   g->cls_begin[kLayouts] = (int32_t)g->work.size();
-  g->config = config;
   size_t off = 0;
   g->lays.clear();
   for (auto* p : g->plans) {
@@ -1090,13 +1102,22 @@ static int group_configure(tamm_group* g, int config) {
   g->off_sitems = off;
   off = align256(off + g->sitem_prob.size() * 2 * sizeof(int32_t));
   g->off_work = off;
-  off = align256(off + g->work.size() * sizeof(WorkItem));
+  // room for any mix of per-class configurations, so the autotuner's choice always fits the
+  // workspace sized for the candidates
+  off = align256(off + std::max(g->work.size(), g->work_capacity) * sizeof(WorkItem));
   g->off_counter = off;  // one work counter per gather layout
   off = align256(off + kLayouts * sizeof(int32_t));
   g->ws_size = off;
   g->bound = false;
   group_drop_graph(g);
   return TAMM_OK;
+}
+
+// One configuration for every class (< 0: each class's default).
+static int group_configure(tamm_group* g, int config) {
+  int cfgs[kLayouts];
+  for (int c = 0; c < kLayouts; ++c) cfgs[c] = config;
+  return group_configure_classes(g, cfgs);
 }
 
 extern "C" int tamm_group_create(tamm_plan* const* plans, int32_t n, tamm_group** out) {
@@ -1118,6 +1139,18 @@ extern "C" int tamm_group_create(tamm_plan* const* plans, int32_t n, tamm_group*
     }
   }
   g->signature = h;
+  for (int c = 0; c < kLayouts; ++c) {
+    size_t most = 0;
+    for (int k = 0; k < f64_config_count(); ++k) {
+      const F64Config& f = f64_config(k);
+      size_t n = 0;
+      for (auto* p : g->plans)
+        if (gather_layout(p) == c)
+          for (const auto& b : p->blocks) n += (size_t)((b.mext + f.mt - 1) / f.mt) * ((b.next + f.nt - 1) / f.nt);
+      most = std::max(most, n);
+    }
+    g->work_capacity += most;
+  }
   const int rc = group_configure(g.get(), -1);
   if (rc != TAMM_OK) return rc;
   *out = g.release();
@@ -1166,20 +1199,37 @@ extern "C" int tamm_group_set_config(tamm_group* g, int32_t config, int32_t grid
   if (grid < 0) return fail(TAMM_ERR_ARG, "grid must be >= 0");
   const int rc = group_configure(g, config);
   if (rc != TAMM_OK) return rc;
-  g->grid = grid;
+  for (int c = 0; c < kLayouts; ++c) g->grid[c] = grid;
   return ok();
 }
 
 // Persistent grid of one layout class: the tuned size, else every resident slot of the device
 // (compute units x resident workgroups of the configuration).
 static int group_grid(const tamm_group* g, int layout, int n_work) {
-  if (g->grid > 0) return std::max(1, std::min<int>(g->grid, n_work));
+  if (g->grid[layout] > 0) return std::max(1, std::min<int>(g->grid[layout], n_work));
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
   }
-  return std::max(1, std::min<int>(f64_occupancy(g->config, layout) * cus, n_work));
+  return std::max(1, std::min<int>(f64_occupancy(g->cfg[layout], layout) * cus, n_work));
+}
+
+// The persistent contraction launch of one layout class (counter reset first); nothing for an
+// empty class.  Consumes the last screening results.
+static int group_enqueue_class(tamm_group* g, int c, hipStream_t s) {
+  const int n = g->cls_begin[c + 1] - g->cls_begin[c];
+  if (n <= 0) return TAMM_OK;
+  const int grid = group_grid(g, c, n);
+  int32_t* counter = (int32_t*)(g->ws + g->off_counter) + c;
+  HIP_TRY(launch_set_counter(counter, grid, s));
+  ContractParams cp{};
+  cp.probs = (const ProblemDesc*)(g->ws + g->off_pdesc);
+  cp.work = (const WorkItem*)(g->ws + g->off_work) + g->cls_begin[c];
+  cp.next_item = counter;
+  cp.n_work = n;
+  HIP_TRY(launch_contract_f64(g->cfg[c], c, cp, grid, s));
+  return TAMM_OK;
 }
 
 // Enqueue the group's kernels (counter reset, screening, persistent contraction).
@@ -1192,17 +1242,8 @@ static int group_enqueue(tamm_group* g, hipStream_t s) {
   HIP_TRY(launch_screen(sp, s));
   // one persistent launch per gather layout present in the group
   for (int c = 0; c < kLayouts; ++c) {
-    const int n = g->cls_begin[c + 1] - g->cls_begin[c];
-    if (n <= 0) continue;
-    const int grid = group_grid(g, c, n);
-    int32_t* counter = (int32_t*)(g->ws + g->off_counter) + c;
-    HIP_TRY(launch_set_counter(counter, grid, s));
-    ContractParams cp{};
-    cp.probs = (const ProblemDesc*)(g->ws + g->off_pdesc);
-    cp.work = (const WorkItem*)(g->ws + g->off_work) + g->cls_begin[c];
-    cp.next_item = counter;
-    cp.n_work = n;
-    HIP_TRY(launch_contract_f64(g->config, c, cp, grid, s));
+    const int rc = group_enqueue_class(g, c, s);
+    if (rc != TAMM_OK) return rc;
   }
   return TAMM_OK;
 }
@@ -1318,42 +1359,59 @@ extern "C" int tamm_group_autotune(tamm_group* g, void* stream, const char* cach
   void* ws = g->ws;
   const size_t bytes = g->ws_bytes;
   hipStream_t s = (hipStream_t)stream;
-  CacheEntry best{-1, 1, 0, 1e30};
-  if (!cache_lookup(cache_path, g->signature, "group", best)) {
+  // per gather layout class, the fastest (configuration, grid) of the class's own launch
+  CacheEntry best[kLayouts];
+  char tag[kLayouts][16];
+  bool cached = true;
+  for (int c = 0; c < kLayouts; ++c) {
+    best[c] = CacheEntry{-1, 1, 0, 1e30};
+    snprintf(tag[c], sizeof(tag[c]), "group%d", c);
+    cached = cache_lookup(cache_path, g->signature, tag[c], best[c]) && cached;
+  }
+  if (!cached) {
     if (reps <= 0) reps = 3;
+    for (int c = 0; c < kLayouts; ++c) best[c] = CacheEntry{-1, 1, 0, 1e30};
     std::vector<double> a0(g->plans.size(), 0.0), b1(g->plans.size(), 1.0);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     int cus = 256, dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    for (int c = 0; c < f64_config_count() && rc == TAMM_OK; ++c) {
+    for (int k = 0; k < f64_config_count() && rc == TAMM_OK; ++k) {
       for (int mult : {0, 1, 2, 4}) {  // 0: every resident slot (occupancy-sized grid)
-        if ((rc = group_configure(g, c)) != TAMM_OK) break;
+        if ((rc = group_configure(g, k)) != TAMM_OK) break;
         if (g->ws_size > bytes) continue;
-        g->grid = mult * cus;
+        for (int c = 0; c < kLayouts; ++c) g->grid[c] = mult * cus;
         if ((rc = group_bind(g, ws, bytes)) != TAMM_OK) break;
-        // alpha = 0, beta = 1 leaves every output unchanged (finite operands)
+        // screening and a warm-up; alpha = 0, beta = 1 leaves every output unchanged (finite
+        // operands), and the classes' launches below reuse that screening
         if ((rc = tamm_group_execute(g, a0.data(), b1.data(), stream)) != TAMM_OK) break;
-        HIP_TRY(hipEventRecord(e0, s));
-        for (int r = 0; r < reps && rc == TAMM_OK; ++r) rc = tamm_group_execute(g, a0.data(), b1.data(), stream);
-        HIP_TRY(hipEventRecord(e1, s));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        ms /= reps;
-        if (ms < best.ms) best = CacheEntry{c, 1, g->grid, ms};
+        for (int c = 0; c < kLayouts && rc == TAMM_OK; ++c) {
+          if (g->cls_begin[c + 1] == g->cls_begin[c]) continue;
+          HIP_TRY(hipEventRecord(e0, s));
+          for (int r = 0; r < reps && rc == TAMM_OK; ++r) rc = group_enqueue_class(g, c, s);
+          HIP_TRY(hipEventRecord(e1, s));
+          HIP_TRY(hipEventSynchronize(e1));
+          float ms = 0;
+          HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+          ms /= reps;
+          if (ms < best[c].ms) best[c] = CacheEntry{k, 1, mult * cus, ms};
+        }
       }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != TAMM_OK) return rc;
-    if (best.config < 0) return fail(TAMM_ERR_WORKSPACE, "no configuration fits the bound workspace");
-    cache_store(cache_path, g->signature, "group", best);
+    for (int c = 0; c < kLayouts; ++c)
+      if (g->cls_begin[c + 1] != g->cls_begin[c] && best[c].config < 0)
+        return fail(TAMM_ERR_WORKSPACE, "no configuration fits the bound workspace");
+    for (int c = 0; c < kLayouts; ++c) cache_store(cache_path, g->signature, tag[c], best[c]);
   }
-  rc = group_configure(g, best.config);
+  int cfgs[kLayouts];
+  for (int c = 0; c < kLayouts; ++c) cfgs[c] = best[c].config;  // < 0 (empty class): default
+  rc = group_configure_classes(g, cfgs);
   if (rc != TAMM_OK) return rc;
-  g->grid = best.grid;
+  for (int c = 0; c < kLayouts; ++c) g->grid[c] = best[c].config >= 0 ? best[c].grid : 0;
   if (g->ws_size > bytes) return fail(TAMM_ERR_WORKSPACE, "cached configuration needs %zu bytes", g->ws_size);
   rc = group_bind(g, ws, bytes);
   return rc == TAMM_OK ? ok() : rc;
@@ -1361,8 +1419,12 @@ extern "C" int tamm_group_autotune(tamm_group* g, void* stream, const char* cach
 
 extern "C" int tamm_group_stats(const tamm_group* g, int32_t* config, int32_t* grid, int64_t* work_items) {
   if (!g) return fail(TAMM_ERR_ARG, "null group");
-  if (config) *config = g->config;
-  if (grid) *grid = g->grid;
+  // the class with the most work items speaks for the group
+  int big = 0;
+  for (int c = 1; c < kLayouts; ++c)
+    if (g->cls_begin[c + 1] - g->cls_begin[c] > g->cls_begin[big + 1] - g->cls_begin[big]) big = c;
+  if (config) *config = g->cfg[big];
+  if (grid) *grid = g->grid[big];
   if (work_items) *work_items = (int64_t)g->work.size();
   return ok();
 }

@@ -55,6 +55,7 @@ def test_group_matches_oracle_and_single_launches_bitwise():
     assert len({m["desc"]["term"] for m in members}) >= 4
     group = tm.Group([m["plan"] for m in members])
     cfg = group.stats()["config"]
+    group.set_config(cfg)  # one configuration for every gather layout class
     alphas = [m["alpha"] for m in members]
     group.execute(alphas, [0.0] * len(members))
     torch.cuda.synchronize()
@@ -124,7 +125,11 @@ def test_autotune_plan_and_group(tmp_path):
         rel, _ = max_rel(x["O"].to_blocks(), oracle_blocks(x, tiles), keys=tiles)
         assert rel <= 1e-12
     lines = open(cache).read().strip().splitlines()
-    assert any(" plan " in ln for ln in lines) and any(" group " in ln for ln in lines)
+    assert any(" plan " in ln for ln in lines)
+    # one entry per gather layout class of the group
+    assert sorted(ln.split()[1] for ln in lines if ln.split()[1].startswith("group")) == [f"group{c}" for c in range(8)]
+    # members of more than one class, each class with its own launch and configuration
+    assert len({x["plan"].stats()["gather_layout"] for x in members}) >= 2
 
 
 def test_group_rejects_dependent_members():
