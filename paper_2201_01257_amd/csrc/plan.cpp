@@ -1001,8 +1001,9 @@ extern "C" int tamm_plan_autotune(tamm_plan* p, void* workspace, size_t bytes, v
 }
 
 // ---------------------------------------------------------------------------------------------
-// groups: many independent plans, one screening launch and one persistent contraction launch,
-// optionally captured once into a hipGraph and replayed.
+// groups: many independent plans, one screening launch and one persistent contraction launch per
+// gather layout class (each with its own configuration), optionally captured once into a hipGraph
+// and replayed.
 // ---------------------------------------------------------------------------------------------
 struct tamm_group {
   std::vector<tamm_plan*> plans;
