@@ -63,16 +63,19 @@ def kernel_source_digest() -> str:
 def measured_traffic(workload: str, config_name: str, work_items: int):
     """HBM bytes per launch of the ladder contraction (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
     from the committed counter record, if it was taken on these kernel sources with the same
-    configuration and work decomposition; otherwise None."""
+    configuration and work decomposition (the record keeps one entry per measured configuration
+    and K split); otherwise None."""
     try:
         with open(TRAFFIC_RECORD) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if (rec.get("source_sha256") != kernel_source_digest() or rec.get("workload") != workload
-            or rec.get("config") != config_name or rec.get("work_items") != work_items):
+    if rec.get("source_sha256") != kernel_source_digest() or rec.get("workload") != workload:
         return None
-    return int(rec["hbm_bytes_per_launch"])
+    for e in rec.get("entries", []):
+        if e.get("config") == config_name and e.get("work_items") == work_items:
+            return int(e["hbm_bytes_per_launch"])
+    return None
 
 
 def build_inputs(torch, tm, synth, wl):
@@ -115,6 +118,9 @@ def main():
     ap.add_argument("--precision", default=None, help="mixed workload: one of f64,f32,bf16x3,bf16x4_aligned (default all)")
     ap.add_argument("--tune-cache", default="", help="autotuner cache file")
     ap.add_argument("--no-tune", action="store_true", help="keep the plans' default kernel configurations")
+    ap.add_argument("--ladder-k-splits", type=int, default=0,
+                    help="after tuning, run the ladder with this many K splits (0: the tuned choice); for "
+                         "counter runs of a second decomposition")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1 "
@@ -162,6 +168,9 @@ def main():
             log(f"[bench] tuned {term}: config {plans[term].config_name()} k_splits {st['k_splits']} "
                 f"work {st['work_items']}")
         log(f"[bench] autotuning took {time.time() - t0:.1f}s")
+    if args.ladder_k_splits > 0:
+        plans["ladder"].set_config(plans["ladder"].stats()["kernel_config"], args.ladder_k_splits)
+        log(f"[bench] ladder forced to {args.ladder_k_splits} K splits: work {plans['ladder'].stats()['work_items']}")
     alphas = {t: synth.TERMS[t][3] for t in STEP_TERMS}
     betas = {"hh_int": 0.0, "ladder": 0.0, "ring": 1.0, "hh": 1.0, "t1_v": 1.0, "t1_o": 1.0}
     e_o = torch.from_numpy(orb.e_occ).cuda()
