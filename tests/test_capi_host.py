@@ -191,3 +191,37 @@ def test_gather_layout_pairs_only_for_adjacent_table_pairs():
     # an odd tile size on the stride-1 labels -> 8-byte gathers
     odd = term_structures("ladder", (11, 11, 11), (15, 4, 15), None)[0]
     assert not tm.Plan(*odd, bind=False).stats()["gather_layout"] & 4
+
+
+def test_group_classes_and_workspace_independent_of_configuration():
+    # members of two gather layout classes (ladder: A k-contiguous; t1_v: neither operand is);
+    # one configuration for all classes or each class's default, the workspace size is the same
+    o = tm.Space.spin(6, 6, 4)
+    v = tm.Space.spin(10, 10, 5)
+    plans = []
+    for term in ("ladder", "t1_v", "ring"):
+        (on, op, ol), (ln, lp, ll), (rn, rp, rl), _ = TERMS[term]
+        sp = {"o": o, "v": v}
+        mk = lambda pat: tm.Tensor([sp[c] for c in pat], device=None)  # noqa: E731
+        plans.append(tm.Plan(mk(op), ol, mk(lp), ll, mk(rp), rl, bind=False))
+    layouts = {p.stats()["gather_layout"] for p in plans}
+    assert len(layouts) >= 2
+    lib = _lib.load()
+    arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+    g = ctypes.c_void_p()
+    assert lib.tamm_group_create(arr, len(plans), ctypes.byref(g)) == 0
+    try:
+        sizes = set()
+        n = ctypes.c_size_t()
+        for c in [-1] + list(range(plans[0].config_count())):
+            assert lib.tamm_group_set_config(g, c, 0) == 0
+            assert lib.tamm_group_workspace_size(g, ctypes.byref(n)) == 0
+            sizes.add(n.value)
+            cfg, grid, items = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+            assert lib.tamm_group_stats(g, ctypes.byref(cfg), ctypes.byref(grid), ctypes.byref(items)) == 0
+            assert items.value > 0 and (c < 0 or cfg.value == c)
+        assert len(sizes) == 1
+        assert lib.tamm_group_set_config(g, 999, 0) == -1
+        assert lib.tamm_group_set_config(g, 0, -1) == -1
+    finally:
+        lib.tamm_group_destroy(g)
