@@ -254,6 +254,40 @@ int tamm_plan_split_operand(const tamm_plan* p, int32_t which, void* out_dev, si
 int tamm_plan_destroy(tamm_plan* p);
 
 /* ------------------------------------------------------------------------------------------
+ * One-shot contraction (the assignment and update statements of Sec. III-A, Fig. 3, issued
+ * one at a time): out(out_lbl) = beta * out + alpha * lhs(lhs_lbl) * rhs(rhs_lbl), with the
+ * semantics of tamm_plan_create / tamm_plan_execute.  The library keeps one plan per distinct
+ * (out, lhs, rhs handles, labels, precision) in a process-wide cache, created on first use with
+ * the default kernel configuration; tamm_tensor_destroy drops every cached plan naming that
+ * tensor.  The cache is guarded by a lock: concurrent calls are serialised on the host.
+ *
+ * tamm_contract_workspace_size creates the cached plan if needed (host only, no GPU call) and
+ * gives the bytes of device workspace tamm_contract needs for it.
+ *
+ * tamm_contract enqueues the contraction on stream.  `workspace`: caller-owned device memory,
+ * 256-byte aligned, of at least that size (ERR_WORKSPACE otherwise).  The plan's tables are
+ * uploaded into it (synchronous copy) unless the previous tamm_contract call given this same
+ * (workspace, bytes) was for the same contraction, which then reuses them; so the library owns
+ * the contents of a workspace between calls, and a caller that writes it or frees and reuses
+ * the memory for another purpose calls tamm_contract_cache_clear before passing it again.
+ * Handing one workspace to another contraction synchronises stream before the upload (an
+ * earlier call may still read the old tables); calls that share a workspace on different
+ * streams must be ordered by the caller; workspaces of different calls are identical or
+ * disjoint.  A separate workspace per contraction keeps repeated calls asynchronous.
+ * Errors of plan creation (labels, shapes) are returned as by tamm_plan_create.
+ *
+ * tamm_contract_cache_count gives the number of cached plans; tamm_contract_cache_clear
+ * drops them all (host memory only; work already enqueued is unaffected).
+ * ------------------------------------------------------------------------------------------ */
+int tamm_contract_workspace_size(tamm_tensor* out, const char* out_lbl, const tamm_tensor* lhs, const char* lhs_lbl,
+                                 const tamm_tensor* rhs, const char* rhs_lbl, int32_t precision, size_t* bytes);
+int tamm_contract(tamm_tensor* out, const char* out_lbl, const tamm_tensor* lhs, const char* lhs_lbl,
+                  const tamm_tensor* rhs, const char* rhs_lbl, int32_t precision, double alpha, double beta,
+                  void* workspace, size_t bytes, void* stream);
+int tamm_contract_cache_count(int64_t* plans);
+int tamm_contract_cache_clear(void);
+
+/* ------------------------------------------------------------------------------------------
  * Groups: many independent plans executed together (the single-GPU analogue of running the
  * operations of one scheduler level at once, Sec. III-B): one screening launch over every
  * member, then one persistent contraction launch whose workgroups take output tiles of all

@@ -23,7 +23,7 @@ contraction, defined as follows (every narrowing rounds to nearest, ties to even
 The result of a split is given as one 64-bit word per element: slice s as bfloat16 bits in bits
 16s..16s+15.
 
-Pins (tests/test_oracle_pins.py): ties and carries of the rounding against an independent
+Pins (tests/test_oracle_split.py): ties and carries of the rounding against an independent
 integer route on float32 bit patterns; reconstruction bounds of both splits (closed forms);
 exactness of the lead slice in bfloat16; window boundaries; the flattening-order rule on the
 contraction shapes of the doubles terms.

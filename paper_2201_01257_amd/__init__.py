@@ -8,6 +8,8 @@ thin Python binding; importing it does not load the native library, the first ca
 fails loudly if the library has not been built.
 """
 
-from .core import Denominator, Group, Plan, Space, TammError, Tensor, contract  # noqa: F401
+from .core import (Denominator, Group, Plan, Space, TammError, Tensor, contract, contract_cache_clear,  # noqa: F401
+                   contract_cache_count)
 
-__all__ = ["Space", "Tensor", "Plan", "Group", "contract", "Denominator", "TammError"]
+__all__ = ["Space", "Tensor", "Plan", "Group", "contract", "contract_cache_count", "contract_cache_clear", "Denominator",
+           "TammError"]

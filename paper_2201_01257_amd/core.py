@@ -331,17 +331,37 @@ class Plan:
 
 
 def contract(out: Tensor, ol: str, lhs: Tensor, ll: str, rhs: Tensor, rl: str, alpha: float = 1.0,
-             beta: float = 0.0, precision: str = "f64") -> Plan:
-    """out(ol) = beta*out(ol) + alpha * lhs(ll) * rhs(rl) on the GPU, with a plan cache on ``out``."""
+             beta: float = 0.0, precision: str = "f64", stream=None) -> Tensor:
+    """out(ol) = beta*out(ol) + alpha * lhs(ll) * rhs(rl) on the GPU through tamm_contract, whose
+    plan cache lives in the library.  Each distinct contraction keeps its own workspace on ``out``
+    (and holds ``lhs`` and ``rhs`` as long as ``out`` lives), so repeated calls stay asynchronous.
+    Returns ``out``."""
+    lib = load()
     key = (ol, id(lhs), ll, id(rhs), rl, precision)
     ent = out._plans.get(key)
     if ent is None or ent[0] is not lhs or ent[1] is not rhs:
-        plan = Plan(out, ol, lhs, ll, rhs, rl, precision)
-        out._plans[key] = (lhs, rhs, plan)
-    else:
-        plan = ent[2]
-    plan.execute(alpha, beta)
-    return plan
+        n = ctypes.c_size_t()
+        check(lib.tamm_contract_workspace_size(out._h, ol.encode(), lhs._h, ll.encode(), rhs._h, rl.encode(),
+                                               PRECISIONS[precision], ctypes.byref(n)))
+        ws, ptr = _aligned_workspace(n.value, out.data.device)
+        ent = (lhs, rhs, ws, ptr, n.value)
+        out._plans[key] = ent
+    s = current_stream_handle() if stream is None else stream
+    check(lib.tamm_contract(out._h, ol.encode(), lhs._h, ll.encode(), rhs._h, rl.encode(), PRECISIONS[precision],
+                            float(alpha), float(beta), ctypes.c_void_p(ent[3]), ent[4], s))
+    return out
+
+
+def contract_cache_count() -> int:
+    """Number of one-shot plans in the library's cache."""
+    n = ctypes.c_int64()
+    check(load().tamm_contract_cache_count(ctypes.byref(n)))
+    return n.value
+
+
+def contract_cache_clear() -> None:
+    """Drop every cached one-shot plan (and forget what each workspace holds)."""
+    check(load().tamm_contract_cache_clear())
 
 
 class Denominator:

@@ -210,6 +210,7 @@ extern "C" int tamm_tensor_bind(tamm_tensor* t, void* dev_ptr, size_t bytes) {
 }
 
 extern "C" int tamm_tensor_destroy(tamm_tensor* t) {
+  if (t) tamm::contract_cache_evict(t);
   delete t;
   return ok();
 }

@@ -16,6 +16,9 @@ namespace tamm {
 int fail(int code, const char* fmt, ...);
 int ok();
 
+// Drops the cached one-shot plans that name tensor t (called when t is destroyed).
+void contract_cache_evict(const tamm_tensor* t);
+
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SpaceData {

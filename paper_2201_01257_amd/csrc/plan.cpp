@@ -8,8 +8,10 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "host.h"
@@ -896,6 +898,122 @@ extern "C" int tamm_plan_split_operand(const tamm_plan* p, int32_t which, void* 
 
 extern "C" int tamm_plan_destroy(tamm_plan* p) {
   delete p;
+  return ok();
+}
+
+// ---------------------------------------------------------------------------------------------
+// one-shot contraction: plans cached inside the library, keyed by tensor handles and labels
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+struct ContractKey {
+  const tamm_tensor* out;
+  const tamm_tensor* lhs;
+  const tamm_tensor* rhs;
+  std::string labels;  // out, lhs and rhs labels joined by '/'
+  int32_t precision;
+  bool operator<(const ContractKey& o) const {
+    return std::tie(out, lhs, rhs, labels, precision) < std::tie(o.out, o.lhs, o.rhs, o.labels, o.precision);
+  }
+};
+
+struct ContractCache {
+  std::mutex mu;
+  std::map<ContractKey, std::unique_ptr<tamm_plan>> plans;
+  std::map<const void*, const tamm_plan*> holder;  // workspace start -> the plan whose tables it holds
+};
+
+// Never destroyed: tensor handles may be released from other static destructors at exit.
+ContractCache& contract_cache() {
+  static ContractCache* c = new ContractCache;
+  return *c;
+}
+
+// The cached plan for a contraction, created on first use.  The caller holds the cache lock.
+int cached_plan(ContractCache& c, tamm_tensor* out, const char* ol, const tamm_tensor* lhs, const char* ll,
+                const tamm_tensor* rhs, const char* rl, int32_t precision, tamm_plan** plan) {
+  if (!out || !lhs || !rhs || !ol || !ll || !rl) return fail(TAMM_ERR_ARG, "null tensor or label string");
+  ContractKey key{out, lhs, rhs, std::string(ol) + "/" + ll + "/" + rl, precision};
+  auto it = c.plans.find(key);
+  if (it != c.plans.end()) {
+    *plan = it->second.get();
+    return TAMM_OK;
+  }
+  tamm_plan* p = nullptr;
+  const int rc = tamm_plan_create(out, ol, lhs, ll, rhs, rl, (tamm_precision)precision, &p);
+  if (rc != TAMM_OK) return rc;
+  c.plans.emplace(std::move(key), std::unique_ptr<tamm_plan>(p));
+  *plan = p;
+  return TAMM_OK;
+}
+
+}  // namespace
+
+void tamm::contract_cache_evict(const tamm_tensor* t) {
+  ContractCache& c = contract_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  for (auto it = c.plans.begin(); it != c.plans.end();) {
+    if (it->first.out != t && it->first.lhs != t && it->first.rhs != t) {
+      ++it;
+      continue;
+    }
+    for (auto h = c.holder.begin(); h != c.holder.end();) h = h->second == it->second.get() ? c.holder.erase(h) : std::next(h);
+    it = c.plans.erase(it);
+  }
+}
+
+extern "C" int tamm_contract_workspace_size(tamm_tensor* out, const char* out_lbl, const tamm_tensor* lhs,
+                                            const char* lhs_lbl, const tamm_tensor* rhs, const char* rhs_lbl,
+                                            int32_t precision, size_t* bytes) {
+  if (!bytes) return fail(TAMM_ERR_ARG, "null argument");
+  ContractCache& c = contract_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  tamm_plan* p = nullptr;
+  const int rc = cached_plan(c, out, out_lbl, lhs, lhs_lbl, rhs, rhs_lbl, precision, &p);
+  if (rc != TAMM_OK) return rc;
+  *bytes = p->ws_size;
+  return ok();
+}
+
+extern "C" int tamm_contract(tamm_tensor* out, const char* out_lbl, const tamm_tensor* lhs, const char* lhs_lbl,
+                             const tamm_tensor* rhs, const char* rhs_lbl, int32_t precision, double alpha, double beta,
+                             void* workspace, size_t bytes, void* stream) {
+  ContractCache& c = contract_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  tamm_plan* p = nullptr;
+  int rc = cached_plan(c, out, out_lbl, lhs, lhs_lbl, rhs, rhs_lbl, precision, &p);
+  if (rc != TAMM_OK) return rc;
+  const auto h = c.holder.find(workspace);
+  const bool holds = p->ws_bound && p->ws == (char*)workspace && p->ws_bytes == bytes && h != c.holder.end() &&
+                     h->second == p;
+  if (!holds) {
+    if (!workspace || ((uintptr_t)workspace) % 256)
+      return fail(TAMM_ERR_WORKSPACE, "workspace must be non-null and 256-byte aligned");
+    if (bytes < p->ws_size)
+      return fail(TAMM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", bytes, p->ws_size);
+    // an earlier call may still be reading the tables this upload replaces
+    if (h != c.holder.end()) HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    c.holder.erase(workspace);
+    rc = bind_plan(p, workspace, bytes);
+    if (rc != TAMM_OK) return rc;
+    c.holder[workspace] = p;
+  }
+  return tamm_plan_execute(p, alpha, beta, stream);
+}
+
+extern "C" int tamm_contract_cache_count(int64_t* plans) {
+  if (!plans) return fail(TAMM_ERR_ARG, "null argument");
+  ContractCache& c = contract_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  *plans = (int64_t)c.plans.size();
+  return ok();
+}
+
+extern "C" int tamm_contract_cache_clear(void) {
+  ContractCache& c = contract_cache();
+  std::lock_guard<std::mutex> lock(c.mu);
+  c.holder.clear();
+  c.plans.clear();
   return ok();
 }
 

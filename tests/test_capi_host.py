@@ -225,3 +225,46 @@ def test_group_classes_and_workspace_independent_of_configuration():
         assert lib.tamm_group_set_config(g, 0, -1) == -1
     finally:
         lib.tamm_group_destroy(g)
+
+
+def test_one_shot_plan_cache_on_the_host():
+    # the cache keys plans by handles, labels and precision; destroying a tensor evicts its plans;
+    # workspace errors are raised before any GPU call
+    lib = _lib.load()
+    assert lib.tamm_contract_cache_clear() == 0
+    o = tm.Space.spin(4, 4, 3)
+    v = tm.Space.spin(7, 7, 4)
+    V = tm.Tensor([v, v, v, v], device=None)
+    T = tm.Tensor([v, v, o, o], device=None)
+    R = tm.Tensor([v, v, o, o], device=None)
+    count = lambda: tm.contract_cache_count()  # noqa: E731
+
+    def ws_size(out, lhs, rhs, labels=(b"abij", b"abcd", b"cdij"), prec=0):
+        n = ctypes.c_size_t()
+        rc = lib.tamm_contract_workspace_size(out._h, labels[0], lhs._h, labels[1], rhs._h, labels[2], prec,
+                                              ctypes.byref(n))
+        return rc, n.value
+
+    rc, n = ws_size(R, V, T)
+    assert rc == 0 and count() == 1
+    assert n == tm.Plan(R, "abij", V, "abcd", T, "cdij", bind=False).workspace_size()
+    assert ws_size(R, V, T) == (0, n) and count() == 1          # cache hit
+    assert ws_size(R, V, T, prec=2)[0] == 0 and count() == 2     # another precision, another plan
+    assert ws_size(R, V, T, labels=(b"abij", b"abcc", b"cdij"))[0] == -2 and count() == 2  # label error, nothing cached
+    # null, misaligned and short workspaces are refused before the upload
+    s0 = ctypes.c_void_p(0)
+    call = lambda ws, nb: lib.tamm_contract(R._h, b"abij", V._h, b"abcd", T._h, b"cdij", 0, 1.0, 0.0,  # noqa: E731
+                                            ctypes.c_void_p(ws), nb, s0)
+    assert call(None, n) == -7
+    assert call(4096 + 8, n) == -7
+    assert call(4096, n - 1) == -7
+    assert count() == 2
+    T2 = tm.Tensor([v, v, o, o], device=None)
+    assert ws_size(R, V, T2)[0] == 0 and count() == 3
+    del T2                                                       # evicts the plan that names it
+    assert count() == 2
+    del R                                                        # evicts both plans for out R
+    assert count() == 0
+    R3 = tm.Tensor([v, v, o, o], device=None)
+    assert ws_size(R3, V, T)[0] == 0 and count() == 1
+    assert lib.tamm_contract_cache_clear() == 0 and count() == 0
