@@ -19,11 +19,13 @@
  *     the ABI.  On failure tamm_last_error() returns a message for the calling thread.
  *   - Device memory is owned by the caller.  The library never allocates device memory: the
  *     caller binds tensor storage (tamm_tensor_bind) and plan/group workspace
- *     (tamm_plan_bind_workspace, tamm_group_bind_workspace).  Handles own host metadata only.
+ *     (tamm_plan_bind_workspace, tamm_group_bind_workspace) or passes it (tamm_contract).
+ *     Handles own host metadata only.
  *   - Asynchronous calls take a hipStream_t (passed as void*; NULL = the null stream), enqueue
  *     their kernels on it and return without synchronising.  HIP launch errors are reported
  *     as TAMM_ERR_HIP.
- *   - Handles are not thread-safe; distinct handles may be used from distinct threads.
+ *   - Handles are not thread-safe; distinct handles may be used from distinct threads.  The
+ *     one-shot plan cache behind tamm_contract is shared and lock-guarded.
  *   - Labels are strings of ASCII letters, one per tensor dimension, no letter twice in one
  *     tensor.  In a contraction every letter appears in exactly two of the three tensors and
  *     binds the same tiled space (same tile sizes and spins) wherever it appears.
@@ -150,6 +152,8 @@ int tamm_tensor_blocks(const tamm_tensor* t, int64_t* nblocks, int32_t* tile_idx
  * not 8-byte aligned. */
 int tamm_tensor_bind(tamm_tensor* t, void* dev_ptr, size_t bytes);
 
+/* Releases the handle (host memory only) and drops the cached one-shot plans (tamm_contract)
+ * that name it.  Plans and groups created by the caller must be destroyed first. */
 int tamm_tensor_destroy(tamm_tensor* t);
 
 /* ------------------------------------------------------------------------------------------
