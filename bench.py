@@ -380,10 +380,12 @@ def cpu_baseline_and_parity(args, torch, tm, synth, orb, g, T, plans, alphas):
     if worst > 1e-12:
         raise SystemExit(f"parity failure against the oracle: {rel_out}")
     cpu = None
+    whole = all(not order[t] for t in STEP_TERMS)
     if not args.no_cpu_baseline:
         cpu = {"value": round(flops / spent / 1e12, 5), "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
                "sample": f"{sum(nblocks.values())} seeded output blocks of the same six terms "
-                         f"({nblocks}), {flops / 1e9:.1f} GFLOP useful, {spent:.1f} s; input generation not timed",
+                         f"({nblocks}{'; every stored block, so the whole step' if whole else ''}), "
+                         f"{flops / 1e9:.1f} GFLOP useful, {spent:.1f} s; input generation not timed",
                "seconds": round(spent, 2)}
     log(f"[bench] parity on sampled blocks: {rel_out}")
     return cpu, {t: float(f"{v:.3e}") for t, v in rel_out.items()}
