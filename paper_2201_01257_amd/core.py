@@ -130,7 +130,7 @@ class Tensor:
             check(lib.tamm_tensor_blocks(self._h, ctypes.byref(nb), self.block_tiles.ctypes.data,
                                          self.block_off.ctypes.data))
         self.data = None
-        self._plans: Dict[tuple, tuple] = {}
+        self._contract_ws: Dict[tuple, tuple] = {}  # contract(): workspace per distinct contraction
         if device is not None:
             torch = _torch()
             self.data = torch.zeros(max(self.numel, 1), dtype=torch.float64, device=device)
@@ -228,7 +228,7 @@ class Tensor:
         return d
 
     def __del__(self, _d=_destroy):
-        self._plans = {}
+        self._contract_ws = {}
         _d(self, "tamm_tensor_destroy")
 
 
@@ -338,14 +338,14 @@ def contract(out: Tensor, ol: str, lhs: Tensor, ll: str, rhs: Tensor, rl: str, a
     Returns ``out``."""
     lib = load()
     key = (ol, id(lhs), ll, id(rhs), rl, precision)
-    ent = out._plans.get(key)
+    ent = out._contract_ws.get(key)
     if ent is None or ent[0] is not lhs or ent[1] is not rhs:
         n = ctypes.c_size_t()
         check(lib.tamm_contract_workspace_size(out._h, ol.encode(), lhs._h, ll.encode(), rhs._h, rl.encode(),
                                                PRECISIONS[precision], ctypes.byref(n)))
         ws, ptr = _aligned_workspace(n.value, out.data.device)
         ent = (lhs, rhs, ws, ptr, n.value)
-        out._plans[key] = ent
+        out._contract_ws[key] = ent
     s = current_stream_handle() if stream is None else stream
     check(lib.tamm_contract(out._h, ol.encode(), lhs._h, ll.encode(), rhs._h, rl.encode(), PRECISIONS[precision],
                             float(alpha), float(beta), ctypes.c_void_p(ent[3]), ent[4], s))

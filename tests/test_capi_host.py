@@ -268,3 +268,38 @@ def test_one_shot_plan_cache_on_the_host():
     R3 = tm.Tensor([v, v, o, o], device=None)
     assert ws_size(R3, V, T)[0] == 0 and count() == 1
     assert lib.tamm_contract_cache_clear() == 0 and count() == 0
+
+
+def test_one_shot_plan_cache_from_several_threads():
+    # the cache lock: threads asking for the same and for distinct contractions at once end with
+    # one cached plan per distinct key and identical sizes for identical keys
+    import threading
+
+    lib = _lib.load()
+    assert lib.tamm_contract_cache_clear() == 0
+    o = tm.Space.spin(4, 4, 3)
+    v = tm.Space.spin(7, 7, 4)
+    V = tm.Tensor([v, v, v, v], device=None)
+    T = tm.Tensor([v, v, o, o], device=None)
+    outs = [tm.Tensor([v, v, o, o], device=None) for _ in range(4)]
+    sizes = {}
+    errors = []
+
+    def work(i):
+        for rep in range(20):
+            out = outs[(i + rep) % len(outs)]
+            n = ctypes.c_size_t()
+            rc = lib.tamm_contract_workspace_size(out._h, b"abij", V._h, b"abcd", T._h, b"cdij", 0, ctypes.byref(n))
+            if rc != 0:
+                errors.append(rc)
+            sizes.setdefault(id(out), set()).add(n.value)
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(8)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert errors == []
+    assert tm.contract_cache_count() == len(outs)
+    assert all(len(s) == 1 for s in sizes.values()) and len({min(s) for s in sizes.values()}) == 1
+    assert lib.tamm_contract_cache_clear() == 0
