@@ -152,9 +152,13 @@ def main():
 
     # ---- plans (analysis once; screening runs inside every step) ----
     plans = {}
+    plan_ms = {}
     for term in STEP_TERMS:
         (on, op, ol), (ln, lp, ll), (rn, rp, rl), a = synth.TERMS[term]
-        plans[term] = tm.Plan(T[on], ol, T[ln], ll, T[rn], rl)
+        h = time.perf_counter()
+        plans[term] = tm.Plan(T[on], ol, T[ln], ll, T[rn], rl, bind=False)  # host analysis only
+        plan_ms[term] = (time.perf_counter() - h) * 1e3
+        plans[term].bind_workspace()
         st = plans[term].stats()
         log(f"[bench] plan {term}: tasks {st['tasks']} useful {st['useful_flops'] / 1e9:.2f} GF "
             f"config {plans[term].config_name()} k_splits {st['k_splits']} work {st['work_items']}")
@@ -188,7 +192,10 @@ def main():
             p = plans[t]
             if evs is not None:
                 evs[t][0].record(stream)
+                evs[t + "/screen"][0].record(stream)
             p.screen()
+            if evs is not None:
+                evs[t + "/screen"][1].record(stream)
             if t == "ladder" and evs is not None:
                 evs["ladder_kernel"][0].record(stream)
             p.contract(alphas[t], betas[t])
@@ -202,7 +209,7 @@ def main():
         if evs is not None:
             evs["denominator"][1].record(stream)
 
-    keys = STEP_TERMS + ["ladder_kernel", "denominator"]
+    keys = STEP_TERMS + [t + "/screen" for t in STEP_TERMS] + ["ladder_kernel", "denominator"]
     events = [{k: (new_ev(), new_ev()) for k in keys} for _ in range(args.steps)]
     t0 = new_ev()
     t1 = new_ev()
@@ -244,7 +251,9 @@ def main():
                        "tflops": round(flops[t] / (ms * 1e-3) / 1e12, 3),
                        "config": plans[t].config_name(), "k_splits": plans[t].stats()["k_splits"],
                        "work_items": plans[t].stats()["work_items"],
-                       "algorithmic_bytes": plans[t].stats()["algorithmic_bytes"]}
+                       "algorithmic_bytes": plans[t].stats()["algorithmic_bytes"],
+                       "screen_ms": round(acc[t + "/screen"] / args.steps, 4),
+                       "plan_ms": round(plan_ms[t], 3)}
     lad_ms = acc["ladder_kernel"] / args.steps
     achieved = flops["ladder"] / (lad_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64_MFMA_TFLOPS, "unit": "TFLOP/s",
@@ -274,6 +283,7 @@ def main():
                    "precision": "f64", "includes": "screening + contraction per term, denominator update",
                    "configs": "autotuned" if not args.no_tune else "default"},
         "step_ms_min": round(min(spans), 4),
+        "step_ms_median": round(float(np.median(spans)), 4),
         "step_ms_max": round(max(spans), 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
