@@ -134,6 +134,8 @@ def main():
         return run_adjoint(args)
     if args.workload == "copycal":
         return run_copycal(args)
+    if args.workload.startswith("dense4d"):
+        return run_dense4d(args)
 
     import torch
 
@@ -669,6 +671,121 @@ def run_adjoint(args):
                  "backward_tflops": round(fl_b / max(fb_ms - f_ms, 1e-9) / 1e9, 3),
                  "useful_gflop": {"forward": round(fl_f / 1e9, 2), "backward": round(fl_b / 1e9, 2)},
                  "note": "forward_backward includes the elementwise loss; parity of these gradients is tested in tests"})
+
+
+def run_dense4d(args):
+    """C(a,b,c,d) += A(a,b,m,n) B(m,n,c,d) with every block stored (the dense 4D comparison
+    contraction of Sec. V), float64, one GPU: each step is one contraction (screening + kernel)."""
+    import torch
+
+    import oracle
+    from paper_2201_01257_amd import core as tm
+    from paper_2201_01257_amd import synth
+
+    wl = synth.DENSE4D[args.workload]
+    n, tile = wl["n"], wl["tile"]
+    orb = synth.dense4d_orbitals(n)
+    sp = tm.Space.fixed(n, tile)
+    X = {}
+    t0 = time.time()
+    for name in ("N_A4", "N_B4"):
+        X[name] = tm.Tensor([sp] * 4)
+        X[name].fill_blocks(lambda lo, ext, out, nm=name: orb.fill(nm, "vvvv", lo, ext, out=out))
+    C = tm.Tensor([sp] * 4)
+    log(f"[bench] dense 4D n={n} tile={tile}: {X['N_A4'].numel} elements per tensor, generated in "
+        f"{time.time() - t0:.1f}s")
+    plan = tm.Plan(C, "abcd", X["N_A4"], "abmn", X["N_B4"], "mncd")
+    if not args.no_tune:
+        # the autotuner on a proxy with the same block shapes and the same summed extent (so the
+        # same work per output tile) but output dimensions of extent proxy_n (its trials at full
+        # size would take minutes); its choice is applied to the full plan
+        pn = wl["proxy_n"]
+        psp = tm.Space.fixed(pn, tile)
+        PA, PB, PC = tm.Tensor([psp, psp, sp, sp]), tm.Tensor([sp, sp, psp, psp]), tm.Tensor([psp] * 4)
+        PA.fill_blocks(lambda lo, ext, out: orb.fill("N_A4", "vvvv", lo, ext, out=out))
+        PB.fill_blocks(lambda lo, ext, out: orb.fill("N_B4", "vvvv", lo, ext, out=out))
+        proxy = tm.Plan(PC, "abcd", PA, "abmn", PB, "mncd")
+        proxy.autotune(args.tune_cache, reps=3)
+        pst = proxy.stats()
+        plan.set_config(pst["kernel_config"], pst["k_splits"])
+        del proxy, PA, PB, PC
+    st = plan.stats()
+    log(f"[bench] plan: {plan.config_name()} k_splits {st['k_splits']} work {st['work_items']} "
+        f"useful {st['useful_flops'] / 1e12:.2f} TF")
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        plan.execute(1.0, 1.0)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(args.steps):
+        plan.screen()
+        ev[i][0].record(stream)
+        plan.contract(1.0, 1.0)
+        ev[i][1].record(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    kms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    fl = st["useful_flops"]
+
+    # parity and the CPU baseline on sampled output blocks (C recomputed with beta = 0)
+    plan.execute(1.0, 0.0)
+    got = C.to_blocks()
+    osp = oracle.Space.fixed(n, tile)
+
+    def otensor(name):
+        x = oracle.BlockTensor([osp] * 4)
+
+        def fill(t):
+            return orb.fill(name, "vvvv", [osp.offsets[i] for i in t], [osp.sizes[i] for i in t])
+
+        x.blocks = oracle.LazyBlocks(fill)
+        return x
+
+    OA, OB, OC = otensor("N_A4"), otensor("N_B4"), oracle.BlockTensor([osp] * 4)
+    rng = np.random.default_rng(2201)
+    tiles = OC.stored_tiles()
+    order = list(rng.permutation(len(tiles)))
+    spent, cflops, picked, ref = 0.0, 0.0, [], {}
+    budget = 0.0 if args.no_cpu_baseline else min(args.cpu_budget, 12.0)
+    ktiles = [(m, nn) for m in range(osp.ntiles) for nn in range(osp.ntiles)]
+    while order and (not picked or spent < budget):
+        tl = tiles[order.pop(0)]
+        for kt in ktiles:  # generate the inputs first, so that only the oracle's work is timed
+            OA.blocks[(tl[0], tl[1]) + kt]
+            OB.blocks[kt + (tl[2], tl[3])]
+        h = time.perf_counter()
+        res = oracle.contract(OC, "abcd", OA, "abmn", OB, "mncd", 1.0, 0.0, out_tiles=[tl])
+        spent += time.perf_counter() - h
+        ref[tl] = res.blocks[tl]
+        cflops += 2.0 * float(np.prod(OC.block_shape(tl))) * n * n
+        picked.append(tl)
+    rel, mx = _rel(got, ref, picked)
+    if rel > 1e-12:
+        raise SystemExit(f"parity failure against the oracle: rel {rel:.3e} (max abs {mx:.3e})")
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count()
+    achieved = fl / (kms * 1e-3) / 1e12
+    line = {"metric": "useful TFLOP/s of the dense 4D contraction", "workload": args.workload,
+            "value": round(fl / (ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "higher_is_better": True,
+            "ms_per_step": round(ms, 3), "steps": args.steps, "warmup": args.warmup, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": args.workload, "n": n, "tile": tile,
+                                            "kernel_config": plan.config_name(), "k_splits": st["k_splits"]},
+            "useful_tflop": round(fl / 1e12, 3),
+            "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64_MFMA_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_MFMA_TFLOPS, 4), "traffic": None,
+                         "kernel": "k_contract_f64 (" + plan.config_name() + ")", "kernel_ms": round(kms, 3)},
+            "rel_err_sampled": float(f"{rel:.3e}"), "sampled_blocks": len(picked),
+            "cpu_baseline": None if args.no_cpu_baseline else {
+                "value": round(cflops / spent / 1e12, 5), "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+                "sample": f"{len(picked)} seeded output blocks of {len(tiles)}, {cflops / 1e9:.1f} GFLOP, {spent:.1f} s; "
+                          "input generation not timed"}}
+    _emit(args, line)
 
 
 def run_copycal(args):

@@ -206,6 +206,21 @@ WORKLOADS = {
     "mixed_o64_v320_t64": dict(n_occ=64, n_vir=320, tile_occ=64, tile_vir=64, terms=["ladder", "ring"]),
 }
 
+# The dense 4D contraction C(a,b,c,d) += A(a,b,m,n) B(m,n,c,d) of the paper's comparison with other
+# tensor frameworks (Sec. V): every dimension of extent n cut into tiles of `tile`, every block
+# stored, inputs N_A4 and N_B4 plain N(0, 0.1^2) over one spin (nothing zeroed).  `proxy_n` is a
+# smaller extent of the output dimensions (same tiles, same summed extent) on which the kernel
+# configuration is tuned.
+DENSE4D = {
+    "dense4d_n200_t40": dict(n=200, tile=40, proxy_n=80),
+    "dense4d_n160_t40": dict(n=160, tile=40, proxy_n=80),
+}
+
+
+def dense4d_orbitals(n: int, seed: int = SEED) -> "Orbitals":
+    """One-spin orbital set of extent n, so that the spin rule stores (and fills) every block."""
+    return Orbitals(2, n, seed=seed, n_occ_alpha=2, n_vir_alpha=n)
+
 
 def batched_problems(seed: int = SEED, count: int = 256):
     """The batched workload: ``count`` independent contractions from random index spaces.
