@@ -136,6 +136,8 @@ def main():
         return run_copycal(args)
     if args.workload.startswith("dense4d"):
         return run_dense4d(args)
+    if args.workload.startswith("tdcc"):
+        return run_complex(args)
 
     import torch
 
@@ -785,6 +787,110 @@ def run_dense4d(args):
                 "value": round(cflops / spent / 1e12, 5), "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
                 "sample": f"{len(picked)} seeded output blocks of {len(tiles)}, {cflops / 1e9:.1f} GFLOP, {spent:.1f} s; "
                           "input generation not timed"}}
+    _emit(args, line)
+
+
+def run_complex(args):
+    """The complex-by-real ladder R(a,b,i,j) += 1/2 V(a,b,c,d) T(c,d,i,j), V real, T and R complex
+    (interleaved, a trailing (re, im) dimension of extent 2), float64; each step one contraction."""
+    import torch
+
+    import oracle
+    from paper_2201_01257_amd import core as tm
+    from paper_2201_01257_amd import synth
+
+    wl = synth.COMPLEX[args.workload]
+    orb = synth.Orbitals(wl["n_occ"], wl["n_vir"])
+    g = {c: _gpu_space(tm, orb, c, wl["tile_occ"] if c == "o" else wl["tile_vir"]) for c in "ov"}
+    g["z"] = tm.Space.fixed(2, 2)
+
+    def spin4(t, sp):
+        return sp[0] + sp[1] == sp[2] + sp[3]
+
+    t0 = time.time()
+    V = tm.Tensor([g[c] for c in "vvvv"])
+    V.fill_blocks(lambda lo, ext, out: orb.fill("V_vvvv", "vvvv", lo, ext, out=out))
+    Tc = tm.Tensor([g[c] for c in "vvooz"], nonzero=spin4)
+    Tc.fill_blocks(lambda lo, ext, out: synth.fill_complex(orb, "T2", "N_T2im", "vvoo", lo, ext, out=out))
+    Rc = tm.Tensor([g[c] for c in "vvooz"], nonzero=spin4)
+    log(f"[bench] complex ladder inputs generated in {time.time() - t0:.1f}s")
+    plan = tm.Plan(Rc, "abijz", V, "abcd", Tc, "cdijz")
+    if not args.no_tune:
+        plan.autotune(args.tune_cache, reps=3)
+    st = plan.stats()
+    fl = st["useful_flops"]
+    log(f"[bench] plan: {plan.config_name()} k_splits {st['k_splits']} work {st['work_items']} "
+        f"useful {fl / 1e9:.1f} GF (real flops)")
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        plan.execute(0.5, 0.0)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(args.steps):
+        plan.screen()
+        ev[i][0].record(stream)
+        plan.contract(0.5, 0.0)
+        ev[i][1].record(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    kms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    got = Rc.to_blocks()
+
+    osp = {c: _oracle_space(oracle, orb, c, wl["tile_occ"] if c == "o" else wl["tile_vir"]) for c in "ov"}
+    osp["z"] = oracle.Space.fixed(2, 2)
+
+    def box(pat, t):
+        return [osp[c].offsets[t[d]] for d, c in enumerate(pat)], [osp[c].sizes[t[d]] for d, c in enumerate(pat)]
+
+    OV = oracle.BlockTensor([osp[c] for c in "vvvv"])
+    OV.blocks = oracle.LazyBlocks(lambda t: orb.fill("V_vvvv", "vvvv", *box("vvvv", t)))
+    OT = oracle.BlockTensor([osp[c] for c in "vvooz"], spin4)
+    OT.blocks = oracle.LazyBlocks(lambda t: synth.fill_complex(orb, "T2", "N_T2im", "vvoo", *box("vvooz", t)))
+    OR = oracle.BlockTensor([osp[c] for c in "vvooz"], spin4)
+    scr = oracle.screen(OR, "abijz", OV, "abcd", OT, "cdijz")
+    tiles = OR.stored_tiles()
+    rng = np.random.default_rng(2201)
+    order = list(rng.permutation(len(tiles)))
+    spent, cflops, picked, ref = 0.0, 0.0, [], {}
+    budget = 0.0 if args.no_cpu_baseline else min(args.cpu_budget, 12.0)
+    while order and (not picked or spent < budget):
+        tl = tiles[order.pop(0)]
+        kts = scr["pairs"][tl]
+        _touch(OR, "abijz", OV, "abcd", OT, "cdijz", tl, kts)
+        h = time.perf_counter()
+        res = oracle.contract(OR, "abijz", OV, "abcd", OT, "cdijz", 0.5, 0.0, out_tiles=[tl])
+        spent += time.perf_counter() - h
+        ref[tl] = res.blocks[tl]
+        for kt in kts:
+            cflops += 2.0 * float(np.prod(OR.block_shape(tl))) * _kext(OV, "abcd", "abijz", kt, "cdijz", OT)
+        picked.append(tl)
+    rel, mx = _rel(got, ref, picked)
+    if rel > 1e-12:
+        raise SystemExit(f"parity failure against the oracle: rel {rel:.3e} (max abs {mx:.3e})")
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count()
+    achieved = fl / (kms * 1e-3) / 1e12
+    line = {"metric": "useful TFLOP/s (real flops) of the complex-by-real ladder", "workload": args.workload,
+            "value": round(fl / (ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "higher_is_better": True,
+            "ms_per_step": round(ms, 4), "steps": args.steps, "warmup": args.warmup, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": args.workload, "n_occ": wl["n_occ"], "n_vir": wl["n_vir"],
+                                            "tile_occ": wl["tile_occ"], "tile_vir": wl["tile_vir"],
+                                            "kernel_config": plan.config_name(), "k_splits": st["k_splits"]},
+            "useful_gflop": round(fl / 1e9, 2),
+            "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64_MFMA_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_MFMA_TFLOPS, 4), "traffic": None,
+                         "kernel": "k_contract_f64 (" + plan.config_name() + ")", "kernel_ms": round(kms, 4)},
+            "rel_err_sampled": float(f"{rel:.3e}"), "sampled_blocks": len(picked),
+            "cpu_baseline": None if args.no_cpu_baseline else {
+                "value": round(cflops / spent / 1e12, 5), "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+                "sample": f"{len(picked)} seeded output blocks of {len(tiles)}, {cflops / 1e9:.1f} GFLOP, "
+                          f"{spent:.1f} s; input generation not timed"}}
     _emit(args, line)
 
 

@@ -217,6 +217,29 @@ DENSE4D = {
 }
 
 
+# The complex-by-real ladder of real-time coupled cluster: R(a,b,i,j) += 1/2 V(a,b,c,d) T(c,d,i,j) with
+# T and R complex and V real.  A complex tensor is stored interleaved (real part, imaginary part),
+# i.e. as a real tensor with one more trailing dimension of extent 2 (one tile of 2), so the
+# contraction is R(a,b,i,j,z) += 1/2 V(a,b,c,d) T(c,d,i,j,z).  Real part of T: the amplitudes T2,
+# imaginary part: N_T2im (plain N(0, 0.1^2), zero where spin is not conserved).
+COMPLEX = {
+    "tdcc_ladder_o40_v200_t40": dict(n_occ=40, n_vir=200, tile_occ=40, tile_vir=40),
+}
+
+
+def fill_complex(orb: "Orbitals", re_name: str, im_name: str, pattern: str, lo: Sequence[int],
+                 ext: Sequence[int], out: Optional[np.ndarray] = None) -> np.ndarray:
+    """Interleaved complex values of a tensor over ``pattern`` plus a trailing (re, im) dimension,
+    on the box lo..lo+ext (the box covers the whole trailing dimension: lo[-1] = 0, ext[-1] = 2)."""
+    if len(lo) != len(pattern) + 1 or int(lo[-1]) != 0 or int(ext[-1]) != 2:
+        raise ValueError("the box must cover the whole (re, im) dimension")
+    if out is None:
+        out = np.empty(tuple(int(e) for e in ext), dtype=np.float64)
+    out[..., 0] = orb.fill(re_name, pattern, lo[:-1], ext[:-1])
+    out[..., 1] = orb.fill(im_name, pattern, lo[:-1], ext[:-1])
+    return out
+
+
 def dense4d_orbitals(n: int, seed: int = SEED) -> "Orbitals":
     """One-spin orbital set of extent n, so that the spin rule stores (and fills) every block."""
     return Orbitals(2, n, seed=seed, n_occ_alpha=2, n_vir_alpha=n)
