@@ -312,11 +312,7 @@ def cpu_baseline_and_parity(args, torch, tm, synth, orb, g, T, plans, alphas):
     import oracle
     from oracle import LazyBlocks
 
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count()
+    threads = _blas_threads()
     osp = {"o": oracle.Space.spin_blocked(orb.n_occ_alpha, orb.n_occ - orb.n_occ_alpha, int(g["o"].sizes.max())),
            "v": oracle.Space.spin_blocked(orb.n_vir_alpha, orb.n_vir - orb.n_vir_alpha, int(g["v"].sizes.max()))}
     rng = np.random.default_rng(2201)
@@ -469,6 +465,35 @@ def _rel(got, ref, keys):
     den = sum(float(np.sum(ref[k] ** 2)) for k in keys)
     mx = max(float(np.max(np.abs(got[k] - ref[k]))) for k in keys)
     return (num / den) ** 0.5 if den > 0 else num ** 0.5, mx
+
+
+def _blas_threads() -> int:
+    """Threads of the host BLAS the oracle runs on."""
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def _time_plan(torch, plan, alpha, beta, steps, warmup):
+    """Per-step time of screening + contraction, and of the contraction alone (HIP events on the
+    launch stream), after `warmup` untimed executions."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.execute(alpha, beta)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        plan.screen()
+        ev[i][0].record(stream)
+        plan.contract(alpha, beta)
+        ev[i][1].record(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, sum(a.elapsed_time(b) for a, b in ev) / steps
 
 
 def _time(torch, fn, steps, warmup):
@@ -714,22 +739,7 @@ def run_dense4d(args):
     st = plan.stats()
     log(f"[bench] plan: {plan.config_name()} k_splits {st['k_splits']} work {st['work_items']} "
         f"useful {st['useful_flops'] / 1e12:.2f} TF")
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        plan.execute(1.0, 1.0)
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for i in range(args.steps):
-        plan.screen()
-        ev[i][0].record(stream)
-        plan.contract(1.0, 1.0)
-        ev[i][1].record(stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    kms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    ms, kms = _time_plan(torch, plan, 1.0, 1.0, args.steps, args.warmup)
     fl = st["useful_flops"]
 
     # parity and the CPU baseline on sampled output blocks (C recomputed with beta = 0)
@@ -767,11 +777,7 @@ def run_dense4d(args):
     rel, mx = _rel(got, ref, picked)
     if rel > 1e-12:
         raise SystemExit(f"parity failure against the oracle: rel {rel:.3e} (max abs {mx:.3e})")
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count()
+    threads = _blas_threads()
     achieved = fl / (kms * 1e-3) / 1e12
     line = {"metric": "useful TFLOP/s of the dense 4D contraction", "workload": args.workload,
             "value": round(fl / (ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "higher_is_better": True,
@@ -821,22 +827,7 @@ def run_complex(args):
     fl = st["useful_flops"]
     log(f"[bench] plan: {plan.config_name()} k_splits {st['k_splits']} work {st['work_items']} "
         f"useful {fl / 1e9:.1f} GF (real flops)")
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        plan.execute(0.5, 0.0)
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for i in range(args.steps):
-        plan.screen()
-        ev[i][0].record(stream)
-        plan.contract(0.5, 0.0)
-        ev[i][1].record(stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    kms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    ms, kms = _time_plan(torch, plan, 0.5, 0.0, args.steps, args.warmup)
     got = Rc.to_blocks()
 
     osp = {c: _oracle_space(oracle, orb, c, wl["tile_occ"] if c == "o" else wl["tile_vir"]) for c in "ov"}
@@ -870,11 +861,7 @@ def run_complex(args):
     rel, mx = _rel(got, ref, picked)
     if rel > 1e-12:
         raise SystemExit(f"parity failure against the oracle: rel {rel:.3e} (max abs {mx:.3e})")
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count()
+    threads = _blas_threads()
     achieved = fl / (kms * 1e-3) / 1e12
     line = {"metric": "useful TFLOP/s (real flops) of the complex-by-real ladder", "workload": args.workload,
             "value": round(fl / (ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "higher_is_better": True,
