@@ -39,6 +39,7 @@ STEP_TERMS = ["hh_int", "ladder", "ring", "hh", "t1_v", "t1_o"]
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "ladder_hbm_traffic.json")
+DENSE4D_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "dense4d_hbm_traffic.json")
 
 
 def log(*a):
@@ -60,13 +61,13 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, config_name: str, work_items: int):
-    """HBM bytes per launch of the ladder contraction (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
-    from the committed counter record, if it was taken on these kernel sources with the same
-    configuration and work decomposition (the record keeps one entry per measured configuration
-    and K split); otherwise None."""
+def measured_traffic(workload: str, config_name: str, work_items: int, record: str = TRAFFIC_RECORD):
+    """HBM bytes per launch of the measured contraction (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+    from a committed counter record (the ladder's by default), if it was taken on these kernel
+    sources with the same workload, configuration and work decomposition (a record keeps one entry
+    per measured configuration and K split); otherwise None."""
     try:
-        with open(TRAFFIC_RECORD) as fh:
+        with open(record) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -786,8 +787,11 @@ def run_dense4d(args):
                                             "kernel_config": plan.config_name(), "k_splits": st["k_splits"]},
             "useful_tflop": round(fl / 1e12, 3),
             "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64_MFMA_TFLOPS,
-                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_MFMA_TFLOPS, 4), "traffic": None,
+                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_MFMA_TFLOPS, 4),
+                         "traffic": measured_traffic(args.workload, plan.config_name(), st["work_items"],
+                                                     DENSE4D_TRAFFIC_RECORD),
                          "kernel": "k_contract_f64 (" + plan.config_name() + ")", "kernel_ms": round(kms, 3)},
+            "algorithmic_bytes": st["algorithmic_bytes"],
             "rel_err_sampled": float(f"{rel:.3e}"), "sampled_blocks": len(picked),
             "cpu_baseline": None if args.no_cpu_baseline else {
                 "value": round(cflops / spent / 1e12, 5), "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
