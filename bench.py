@@ -40,6 +40,7 @@ STEP_TERMS = ["hh_int", "ladder", "ring", "hh", "t1_v", "t1_o"]
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "ladder_hbm_traffic.json")
 DENSE4D_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "dense4d_hbm_traffic.json")
+TDCC_TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "tdcc_hbm_traffic.json")
 
 
 def log(*a):
@@ -875,8 +876,11 @@ def run_complex(args):
                                             "kernel_config": plan.config_name(), "k_splits": st["k_splits"]},
             "useful_gflop": round(fl / 1e9, 2),
             "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64_MFMA_TFLOPS,
-                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_MFMA_TFLOPS, 4), "traffic": None,
+                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_MFMA_TFLOPS, 4),
+                         "traffic": measured_traffic(args.workload, plan.config_name(), st["work_items"],
+                                                     TDCC_TRAFFIC_RECORD),
                          "kernel": "k_contract_f64 (" + plan.config_name() + ")", "kernel_ms": round(kms, 4)},
+            "algorithmic_bytes": st["algorithmic_bytes"],
             "rel_err_sampled": float(f"{rel:.3e}"), "sampled_blocks": len(picked),
             "cpu_baseline": None if args.no_cpu_baseline else {
                 "value": round(cflops / spent / 1e12, 5), "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
