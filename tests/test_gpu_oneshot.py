@@ -6,7 +6,7 @@
 * one workspace shared by two contractions called alternately without host synchronisation:
   bitwise equal to separate plans with their own workspaces (the cache uses the same default
   kernel configuration, so the arithmetic is the same);
-* a split-bfloat16 precision through the cache, bitwise equal to a plan of that precision;
+* each reduced precision through the cache, bitwise equal to a plan of that precision;
 * a tensor destroyed and replaced: the cache drops its plans and the new tensor gets a fresh one.
 """
 
@@ -87,13 +87,14 @@ def test_shared_workspace_alternating_contractions_bitwise():
     del ws_owner
 
 
-def test_split_precision_through_the_cache_bitwise():
+@pytest.mark.parametrize("precision", ["f32", "bf16x3", "bf16x4_aligned"])
+def test_reduced_precision_through_the_cache_bitwise(precision):
     prob = Problem(*SMALL)
     (_, _, ol), (L, ll), (Rh, rl), a = inputs(prob, "ladder")
     O1 = prob.gpu_tensor("R", "vvoo")
     O2 = prob.gpu_tensor("R", "vvoo")
-    tm.contract(O1, ol, L, ll, Rh, rl, a, 0.0, precision="bf16x4_aligned")
-    tm.Plan(O2, ol, L, ll, Rh, rl, precision="bf16x4_aligned").execute(a, 0.0)
+    tm.contract(O1, ol, L, ll, Rh, rl, a, 0.0, precision=precision)
+    tm.Plan(O2, ol, L, ll, Rh, rl, precision=precision).execute(a, 0.0)
     torch.cuda.synchronize()
     assert torch.equal(O1.data, O2.data)
 
