@@ -16,6 +16,7 @@ What it follows (arXiv 2201.01257, "TAMM: Tensor Algebra for Many-body Methods")
   (Sec. III-A, Fig. 3, grammar rule 8) and its ``=`` / ``+=`` / ``-=`` forms;
 * the CCSD doubles terms, the intermediate factorisation of Eqs. (cc9)-(cc11) and its TAMM
   form (Eq. tamm_cc11), spin-explicit sub-spaces (Eq. tamm_cc-Spin), Sec. IV-A-1;
+* the SetOp and AddOp (with a label permutation) of the same grammar (Fig. 3, rules 5-7);
 * the orbital-energy-denominator update that turns a doubles residual into new amplitudes
   (the Jacobi step of CD-CCSD, named in Sec. IV-B-1).
 
@@ -32,6 +33,7 @@ beyond the tolerance each precision states).
 from .tiling import Space, spin_conserving
 from .blocksparse import BlockTensor, LazyBlocks, contract, screen, denominator_update, parse_labels
 from .adjoint import contract_vjp
+from .elementwise import add, set_value
 
 __all__ = [
     "Space",
@@ -43,4 +45,6 @@ __all__ = [
     "denominator_update",
     "parse_labels",
     "contract_vjp",
+    "add",
+    "set_value",
 ]

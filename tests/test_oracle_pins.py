@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import BlockTensor, Space, contract, screen, spin_conserving
+from oracle import BlockTensor, Space, add, contract, screen, set_value, spin_conserving
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -91,11 +91,14 @@ def test_fig4_program_gives_zero():
     tK = Space.fixed(20, 5)
     tN = Space.fixed(100, 10)
     dense_rule = lambda t, s: True  # noqa: E731
-    A = BlockTensor.from_dense([tM, tK], np.ones((30, 20)), dense_rule)        # A(i,l) = 1
-    B = BlockTensor.from_dense([tK, tN], rng.standard_normal((20, 100)), dense_rule)
+    A = set_value(BlockTensor.zeros([tM, tK], dense_rule), 1.0)                 # A(i,l) = 1.0
+    assert all(np.all(b == 1.0) for b in A.blocks.values())
     # B = A ; B += -1 * A  (on B's own, consistent, label binding): B becomes exactly zero
-    B = BlockTensor.from_dense([tK, tN], np.ones((20, 100)), dense_rule)
-    B.blocks = {t: b + (-1.0) * np.ones_like(b) for t, b in B.blocks.items()}
+    A2 = set_value(BlockTensor.zeros([tK, tN], dense_rule), 1.0)
+    B = BlockTensor.from_dense([tK, tN], rng.standard_normal((20, 100)), dense_rule)
+    B = add(B, "la", A2, "la", 1.0, 0.0)                                         # B(l,a) = A(l,a)
+    assert all(np.all(b == 1.0) for b in B.blocks.values())
+    B = add(B, "la", A2, "la", -1.0, 1.0)                                        # B(l,a) += -1.0 * A(l,a)
     assert all(np.all(b == g["expected"]["B"]) for b in B.blocks.values())
     C = BlockTensor.zeros([tM, tN], dense_rule)
     C = contract(C, "ia", A, "il", B, "la", alpha=0.5, beta=0.0)              # C(i,a) = 0.5*A(i,l)*B(l,a)
@@ -453,3 +456,54 @@ def test_denominator_update_elementwise():
     R1d = R1.to_dense()
     for a, i in itertools.product(range(6), range(4)):
         assert T1[a, i] == R1d[a, i] / (e_o[i] - e_v[a])
+
+
+def test_denominator_update_exact_powers_of_two():
+    # energies on a grid where every denominator is minus a power of two: the division is then an
+    # exact scaling, so T' = R * 2^-k holds bitwise (independent of how the quotient is formed)
+    o = Space.spin_blocked(2, 2, 1)
+    v = Space.spin_blocked(2, 2, 1)
+    e_o = np.array([-1.0, -1.0, -1.0, -1.0])
+    e_v = np.array([1.0, 1.0, 3.0, 3.0])          # D = -2 - e_a - e_b in {-4, -6, -8}
+    rng = np.random.default_rng(19)
+    R = BlockTensor.from_dense([v, v, o, o], rng.standard_normal((4, 4, 4, 4)))
+    T = oracle.denominator_update(R, e_o, e_v).to_dense()
+    Rd = R.to_dense()
+    for a, b in itertools.product(range(4), range(4)):
+        s_ab = e_v[a] + e_v[b]
+        if s_ab in (2.0, 6.0):                     # D = -4 or -8
+            assert np.array_equal(T[a, b], Rd[a, b] * (-1.0 / (2.0 + s_ab)))
+    # every quotient times its denominator gives back the residual to within one rounding
+    e_o = rng.uniform(-2, -0.5, 4)
+    e_v = rng.uniform(0.2, 3, 4)
+    T = oracle.denominator_update(R, e_o, e_v).to_dense()
+    D = e_o[None, None, :, None] + e_o[None, None, None, :] - e_v[:, None, None, None] - e_v[None, :, None, None]
+    assert np.all(np.abs(T * D - Rd) <= 2.0 ** -51 * np.abs(Rd))
+    assert np.all(T * Rd <= 0)                     # D < 0 everywhere
+
+
+@pytest.mark.parametrize("term", list(TERM_LABELS))
+def test_sampled_out_tiles_equal_the_full_contraction(term):
+    # the restriction to listed output blocks (used for sampled checks of large problems) gives
+    # exactly the blocks of the full contraction, for every term on ragged tilings
+    rng = np.random.default_rng(sum(map(ord, term)))
+    o = Space.spin_blocked(3, 2, 2)
+    v = Space.spin_blocked(5, 4, 3)
+    out, ol, lhs, ll, rhs, rl = term_tensors(term, o, v)
+    L = BlockTensor.from_dense(lhs.spaces, rng.standard_normal(lhs.shape))
+    Rh = BlockTensor.from_dense(rhs.spaces, rng.standard_normal(rhs.shape))
+    O0 = BlockTensor.from_dense(out.spaces, rng.standard_normal(out.shape))
+    full = contract(O0, ol, L, ll, Rh, rl, 0.75, 0.5)
+    tiles = O0.stored_tiles()
+    pick = [tiles[i] for i in rng.choice(len(tiles), size=min(5, len(tiles)), replace=False)]
+    part = contract(O0, ol, L, ll, Rh, rl, 0.75, 0.5, out_tiles=pick)
+    assert sorted(part.blocks) == sorted(pick)
+    for t in pick:
+        assert np.array_equal(part.blocks[t], full.blocks[t])
+    # and the full contraction itself against dense einsum on exactly these blocks
+    ref = 0.5 * O0.to_dense() + 0.75 * np.einsum(f"{ll},{rl}->{ol}", L.to_dense(), Rh.to_dense())
+    for t in pick:
+        assert rel_err(part.blocks[t], ref[O0.block_slices(t)]) < 1e-13
+    with pytest.raises(ValueError):
+        unstored = next(t for t in O0.all_tiles() if not O0.is_stored(tuple(t)))
+        contract(O0, ol, L, ll, Rh, rl, 1.0, 0.0, out_tiles=[tuple(unstored)])
