@@ -61,7 +61,7 @@ typedef enum {
  *   BF16X3 : each operand split into three bfloat16 terms, x ~ b0 + b1 + b2 with
  *            b_i = bf16(x - b_0 - ... - b_{i-1}) (round to nearest even); the six products
  *            b_i*b_j with i + j <= 2 on bfloat16 matrix cores (v_mfma_f32_16x16x32_bf16),
- *            summed in float32 per window.
+ *            summed in float32 per window: b0*b0 in one accumulator, the other five in another.
  *   BF16X4_ALIGNED : the leading term of every element is x rounded to the fixed-point grid 8
  *            bits below the maximum exponent of its (row, window) -- exact in bfloat16 -- and the
  *            residual is split into three bfloat16 terms; the ten products of term order
@@ -274,10 +274,9 @@ int tamm_plan_destroy(tamm_plan* p);
  * (workspace, bytes) was for the same contraction, which then reuses them; so the library owns
  * the contents of a workspace between calls, and a caller that writes it or frees and reuses
  * the memory for another purpose calls tamm_contract_cache_clear before passing it again.
- * Handing one workspace to another contraction synchronises stream before the upload (an
- * earlier call may still read the old tables); calls that share a workspace on different
- * streams must be ordered by the caller; workspaces of different calls are identical or
- * disjoint.  A separate workspace per contraction keeps repeated calls asynchronous.
+ * Handing a workspace (or memory overlapping one an earlier call used) to another contraction
+ * synchronises the whole device before the upload, since earlier calls on any stream may still
+ * read the old tables.  A separate workspace per contraction keeps repeated calls asynchronous.
  * Errors of plan creation (labels, shapes) are returned as by tamm_plan_create.
  *
  * tamm_contract_cache_count gives the number of cached plans; tamm_contract_cache_clear
@@ -355,6 +354,48 @@ int tamm_denominator_workspace_size(const tamm_denominator* d, size_t* bytes);
 int tamm_denominator_bind_workspace(tamm_denominator* d, void* workspace, size_t bytes);
 int tamm_denominator_execute(tamm_denominator* d, const double* const* energy, void* stream);
 int tamm_denominator_destroy(tamm_denominator* d);
+
+/* ------------------------------------------------------------------------------------------
+ * Element-wise operations of the operation grammar (Sec. III-A, Fig. 3 rules 5-7; the SetOp and
+ * AddOp lines of Fig. 4).  Both run over the stored blocks of out only and are bound by HBM
+ * bandwidth.
+ *
+ * tamm_set (SetOp, rule 5, "A(i,l) = alpha"): every stored element of out becomes alpha.
+ *   Enqueued on stream.  ERR_UNBOUND if out has no storage.
+ *
+ * tamm_add_* (AddOp, rules 6-7, "B(i,l) = A(i,l)", "B(i,l) += -1.0 * A(i,l)", and the addition
+ *   "A(i,l) += alpha * D(l,i)" with a label permutation):
+ *     out(out_lbl) = beta * out(out_lbl) + alpha * in(in_lbl),
+ *   where in_lbl is a permutation of out_lbl and every letter binds the same tiled space in both
+ *   tensors.  For each stored block of out, the block of in at the permuted tile tuple is read
+ *   through the permutation; if that block is not stored it reads as zero (the out block becomes
+ *   beta * out).  beta == 0 never reads out.  "=" is beta = 0, "+=" beta = 1, "-=" alpha -> -alpha.
+ *   Prepared once (host only), bound to a caller-owned workspace (256-byte aligned; the block and
+ *   work tables are copied in synchronously), executed many times.  out and in storage must be
+ *   disjoint, except that with identical label strings they may be the same storage (an
+ *   in-place scale); ERR_ARG at execution otherwise.  ERR_LABEL if in_lbl is not a permutation of
+ *   out_lbl or a letter binds two different spaces; ERR_SHAPE on a rank mismatch.
+ * ------------------------------------------------------------------------------------------ */
+int tamm_set(tamm_tensor* out, double alpha, void* stream);
+
+typedef struct tamm_add tamm_add;
+int tamm_add_create(tamm_tensor* out, const char* out_lbl, const tamm_tensor* in, const char* in_lbl, tamm_add** a);
+int tamm_add_workspace_size(const tamm_add* a, size_t* bytes);
+int tamm_add_bind_workspace(tamm_add* a, void* workspace, size_t bytes);
+int tamm_add_execute(tamm_add* a, double alpha, double beta, void* stream);
+int tamm_add_destroy(tamm_add* a);
+
+/* ------------------------------------------------------------------------------------------
+ * Diagnostic: execute one matrix-core instruction on one wave with caller data (device
+ * pointers, enqueued on stream), for tests of its lane layout and of the rounding of its float32
+ * accumulation on inputs whose exact results are known.  The contraction path never calls it.
+ *   op 0: v_mfma_f32_16x16x4_f32    a, b: 64 floats (one per lane); c, d: 256 floats (4 per lane)
+ *   op 1: v_mfma_f32_16x16x32_bf16  a, b: 512 bfloat16 (8 per lane);  c, d: 256 floats
+ *   op 2: v_mfma_f32_32x32x16_bf16  a, b: 512 bfloat16 (8 per lane);  c, d: 1024 floats (16 per lane)
+ *   op 3: v_mfma_f32_32x32x2_f32    a, b: 64 floats;                   c, d: 1024 floats
+ * d receives the result registers, lane-major like c.  ERR_ARG on an unknown op or a null pointer.
+ * ------------------------------------------------------------------------------------------ */
+int tamm_diag_mfma(int32_t op, const void* a, const void* b, const float* c, float* d, void* stream);
 
 #ifdef __cplusplus
 }

@@ -81,6 +81,13 @@ SIGNATURES = {
     "tamm_denominator_bind_workspace": (c_int, [c_vp, c_vp, c_size_t]),
     "tamm_denominator_execute": (c_int, [c_vp, P(c_vp), c_vp]),
     "tamm_denominator_destroy": (c_int, [c_vp]),
+    "tamm_set": (c_int, [c_vp, c_dbl, c_vp]),
+    "tamm_add_create": (c_int, [c_vp, c_char_p, c_vp, c_char_p, P(c_vp)]),
+    "tamm_add_workspace_size": (c_int, [c_vp, P(c_size_t)]),
+    "tamm_add_bind_workspace": (c_int, [c_vp, c_vp, c_size_t]),
+    "tamm_add_execute": (c_int, [c_vp, c_dbl, c_dbl, c_vp]),
+    "tamm_add_destroy": (c_int, [c_vp]),
+    "tamm_diag_mfma": (c_int, [c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
 }
 
 STATUS = {

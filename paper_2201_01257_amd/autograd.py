@@ -8,7 +8,8 @@ on out's stored blocks:
     d out0 = beta * g.
 
 Both gradients are block-sparse contractions of the same kind as the forward one and run on the
-same HIP kernels (screening, gathers, MFMA, epilogue); the primal operands are re-gathered from
+same HIP kernels (screening, gathers, MFMA, epilogue); d out0 is an AddOp of the library.  The
+primal operands are re-gathered from
 their storage in the backward pass (nothing permuted is saved).  The paper defines no adjoint;
 this is the chain rule applied to the bilinear contraction of Sec. III-A, Fig. 3 rule 8.
 
@@ -21,6 +22,7 @@ from __future__ import annotations
 
 from typing import Dict, Optional, Tuple
 
+import numpy as np
 import torch
 
 from . import core as tm
@@ -33,15 +35,14 @@ class Contraction:
                  alpha: float = 1.0, beta: float = 0.0):
         self.ol, self.ll, self.rl = ol, ll, rl
         self.alpha, self.beta = float(alpha), float(beta)
-        spaces = lambda t: t.spaces  # noqa: E731
-        # private structure handles (re-bound to call storages); storage-less until bound
-        self.S_out = tm.Tensor(spaces(out), device=None)
-        self.S_lhs = tm.Tensor(spaces(lhs), device=None)
-        self.S_rhs = tm.Tensor(spaces(rhs), device=None)
-        self.S_gout = tm.Tensor(spaces(out), device=None)
-        self.S_glhs = tm.Tensor(spaces(lhs), device=None)
-        self.S_grhs = tm.Tensor(spaces(rhs), device=None)
+        # private structure handles (re-bound to call storages); storage-less until bound.  Each
+        # is built from the caller's spaces and non-zero check, so its stored blocks and their
+        # offsets are those of the caller's tensor (checked).
+        self.S_out, self.S_gout, self.S_gout0 = (_clone_structure(out) for _ in range(3))
+        self.S_lhs, self.S_glhs = (_clone_structure(lhs) for _ in range(2))
+        self.S_rhs, self.S_grhs = (_clone_structure(rhs) for _ in range(2))
         self._plans: Dict[str, tm.Plan] = {}
+        self._scale: Optional[tm.Add] = None  # d out0 = beta * g (an AddOp in the library)
 
     def _plan(self, key: str) -> tm.Plan:
         p = self._plans.get(key)
@@ -70,6 +71,16 @@ class Contraction:
 
     def __call__(self, lhs_data: torch.Tensor, rhs_data: torch.Tensor, out0_data: Optional[torch.Tensor] = None):
         return _ContractFn.apply(lhs_data, rhs_data, out0_data, self)
+
+
+def _clone_structure(t: tm.Tensor) -> tm.Tensor:
+    """A storage-less tensor with the spaces and non-zero check of ``t``; its block table and
+    block offsets must equal ``t``'s (so storage laid out for ``t`` binds to it unchanged)."""
+    s = tm.Tensor(t.spaces, nonzero=t.nonzero, device=None)
+    if s.numel != t.numel or not np.array_equal(s.block_tiles, t.block_tiles) or \
+            not np.array_equal(s.block_off, t.block_off):
+        raise ValueError("the tensor's block structure could not be reproduced from its spaces and non-zero check")
+    return s
 
 
 def _bind(struct: tm.Tensor, data: torch.Tensor):
@@ -115,7 +126,13 @@ class _ContractFn(torch.autograd.Function):
             _bind(c.S_grhs, g_rhs)
             c._run("drhs", c.alpha, 0.0, dev)
         if ctx.has_out0 and ctx.needs_input_grad[2]:
-            g_out0 = c.beta * g
+            g_out0 = torch.empty(max(c.S_out.numel, 1), dtype=torch.float64, device=dev)
+            _bind(c.S_gout0, g_out0)
+            if c._scale is None:
+                c._scale = tm.Add(c.S_gout0, c.ol, c.S_gout, c.ol, bind=False)
+            if c._scale._ws is None or c._scale._ws.device != dev:
+                c._scale.bind_workspace(dev)
+            c._scale.execute(c.beta, 0.0)
         return g_lhs, g_rhs, g_out0, None
 
 

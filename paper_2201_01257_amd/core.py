@@ -106,6 +106,7 @@ class Tensor:
         lib = load()
         self.spaces = list(spaces)
         self.rank = len(self.spaces)
+        self.nonzero = nonzero
         arr = (ctypes.c_void_p * self.rank)(*[s._h.value for s in self.spaces])
         h = ctypes.c_void_p()
         cb = None
@@ -391,6 +392,41 @@ class Denominator:
         _d(self, "tamm_denominator_destroy")
 
 
+def set_value(out: Tensor, alpha: float, stream=None) -> Tensor:
+    """SetOp: every stored element of ``out`` becomes ``alpha`` (tamm_set)."""
+    s = current_stream_handle() if stream is None else stream
+    check(load().tamm_set(out._h, float(alpha), s))
+    return out
+
+
+class Add:
+    """AddOp with a label permutation: out(ol) = beta*out(ol) + alpha*in(il) (tamm_add_*)."""
+
+    def __init__(self, out: Tensor, ol: str, inp: Tensor, il: str, bind: bool = True):
+        self.out, self.inp = out, inp  # kept alive as long as the operation
+        self.labels = (ol, il)
+        h = ctypes.c_void_p()
+        check(load().tamm_add_create(out._h, ol.encode(), inp._h, il.encode(), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_size_t()
+        check(load().tamm_add_workspace_size(self._h, ctypes.byref(n)))
+        self.ws_bytes = n.value
+        self._ws = None
+        if bind and out.data is not None:
+            self.bind_workspace(out.data.device)
+
+    def bind_workspace(self, device):
+        self._ws, ptr = _aligned_workspace(self.ws_bytes, device)
+        check(load().tamm_add_bind_workspace(self._h, ctypes.c_void_p(ptr), self.ws_bytes))
+
+    def execute(self, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        s = current_stream_handle() if stream is None else stream
+        check(load().tamm_add_execute(self._h, float(alpha), float(beta), s))
+
+    def __del__(self, _d=_destroy):
+        _d(self, "tamm_add_destroy")
+
+
 class Group:
     """Independent float64 plans executed as one grouped persistent launch (optionally a hipGraph)."""
 
@@ -461,4 +497,4 @@ class Group:
         _d(self, "tamm_group_destroy")
 
 
-__all__ = ["Space", "Tensor", "Plan", "Group", "contract", "Denominator", "TammError", "PRECISIONS"]
+__all__ = ["Space", "Tensor", "Plan", "Group", "contract", "Denominator", "Add", "set_value", "TammError", "PRECISIONS"]

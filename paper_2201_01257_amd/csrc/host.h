@@ -19,6 +19,11 @@ int ok();
 // Drops the cached one-shot plans that name tensor t (called when t is destroyed).
 void contract_cache_evict(const tamm_tensor* t);
 
+// AddOp enqueue (addop.cpp), shared with the scheduler.
+int add_enqueue(tamm_add* a, double alpha, double beta, hipStream_t s);
+const tamm_tensor* add_out(const tamm_add* a);
+const tamm_tensor* add_in(const tamm_add* a);
+
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SpaceData {

@@ -160,6 +160,39 @@ struct DenomParams {
   int64_t n_items;              // workgroups
 };
 
+// AddOp (out = beta*out + alpha*in with permuted labels): one stored block of out and the block
+// of in at the permuted tile tuple.
+struct AddBlock {
+  int64_t out_off;           // element offset of the out block
+  int64_t in_off;            // element offset of the in block; -1: not stored (reads as zero)
+  int32_t ext[kMaxRank];     // extents, out's dimension order
+  int32_t istr[kMaxRank];    // in-block stride of the label of each out dimension
+};
+
+// Work item of the AddOp kernels.  Direct mode (out and in end in the same label): a = first
+// element of a chunk.  Transpose mode: a = batch index over the dimensions other than the two
+// stride-1 ones, b = first row (out dimension ydim), c = first column (out's last dimension).
+struct AddItem {
+  int32_t block, a, b, c;
+};
+
+struct AddParams {
+  double* out;
+  const double* in;
+  const AddBlock* blocks;
+  const AddItem* items;
+  int64_t n_items;
+  double alpha, beta;
+  int32_t rank;
+  int32_t ydim;   // transpose mode: out dimension of in's last label; -1: direct mode
+  int32_t chunk;  // direct mode: elements per item
+  int32_t pad;
+};
+
+hipError_t launch_add(const AddParams& p, hipStream_t s);
+// SetOp: p[0 .. n) = value.
+hipError_t launch_fill(double* p, int64_t n, double value, hipStream_t s);
+
 // Kernel configuration of the FP64 contraction kernel family.
 struct F64Config {
   int mt, nt, kt, wgm, wgn, occ;  // occ: minimum waves per SIMD the registers must allow

@@ -10,7 +10,8 @@
 //       64-bit word per element (slice s in bits 16s..16s+15) at the float64 element offsets; the
 //       contraction then multiplies selected slice pairs.
 //         - three plain slices (x ~ b0 + b1 + b2, b_i = bf16(x - b_0 - ... - b_{i-1})), the six
-//           products b_i*b_j with i + j <= 2, one float32 accumulator per window;
+//           products b_i*b_j with i + j <= 2; b0*b0 in one float32 accumulator per window, the
+//           five smaller products in another;
 //         - aligned lead: slice 0 is x rounded to a fixed-point grid of 8 bits below the maximum
 //           exponent of its (row, window) -- an integer of magnitude <= 256 times a power of two,
 //           exact in bfloat16 -- and slices 1..3 are bfloat16 slices of the residual; the ten
@@ -601,7 +602,9 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[2][j], r, 0, 0, 0);
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2][i], bfr[1][j], r, 0, 0, 0);
             } else {
-              r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[0][j], r, 0, 0, 0);
+              // b0 x b0 carries almost all of the sum: its own accumulator, so that its running
+              // sum is rounded once per k-step rather than once per product plane
+              lead[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[0][j], lead[i][j], 0, 0, 0);
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[1][j], r, 0, 0, 0);
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[0][j], r, 0, 0, 0);
               r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[2][j], r, 0, 0, 0);
@@ -621,7 +624,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
           for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              acc[i][j][r] += ALIGNED ? (double)lead[i][j][r] + (double)rest[i][j][r] : (double)rest[i][j][r];
+              acc[i][j][r] += (double)lead[i][j][r] + (double)rest[i][j][r];
               lead[i][j][r] = 0.f;
               rest[i][j][r] = 0.f;
             }

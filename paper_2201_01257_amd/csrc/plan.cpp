@@ -920,7 +920,11 @@ struct ContractKey {
 struct ContractCache {
   std::mutex mu;
   std::map<ContractKey, std::unique_ptr<tamm_plan>> plans;
-  std::map<const void*, const tamm_plan*> holder;  // workspace start -> the plan whose tables it holds
+  struct Holder {
+    const tamm_plan* plan;  // the plan whose tables the workspace holds
+    size_t bytes;           // the workspace's length
+  };
+  std::map<const void*, Holder> holder;  // workspace start -> its holder
 };
 
 // Never destroyed: tensor handles may be released from other static destructors at exit.
@@ -957,7 +961,7 @@ void tamm::contract_cache_evict(const tamm_tensor* t) {
       ++it;
       continue;
     }
-    for (auto h = c.holder.begin(); h != c.holder.end();) h = h->second == it->second.get() ? c.holder.erase(h) : std::next(h);
+    for (auto h = c.holder.begin(); h != c.holder.end();) h = h->second.plan == it->second.get() ? c.holder.erase(h) : std::next(h);
     it = c.plans.erase(it);
   }
 }
@@ -985,18 +989,29 @@ extern "C" int tamm_contract(tamm_tensor* out, const char* out_lbl, const tamm_t
   if (rc != TAMM_OK) return rc;
   const auto h = c.holder.find(workspace);
   const bool holds = p->ws_bound && p->ws == (char*)workspace && p->ws_bytes == bytes && h != c.holder.end() &&
-                     h->second == p;
+                     h->second.plan == p && h->second.bytes == bytes;
   if (!holds) {
     if (!workspace || ((uintptr_t)workspace) % 256)
       return fail(TAMM_ERR_WORKSPACE, "workspace must be non-null and 256-byte aligned");
     if (bytes < p->ws_size)
       return fail(TAMM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", bytes, p->ws_size);
-    // an earlier call may still be reading the tables this upload replaces
-    if (h != c.holder.end()) HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-    c.holder.erase(workspace);
+    // Earlier calls, on any stream, may still read tables in the range this upload overwrites:
+    // drain the device before replacing them (a rare path: it runs when a workspace changes hands).
+    const char* lo = (const char*)workspace;
+    bool busy = false;
+    for (auto it = c.holder.begin(); it != c.holder.end();) {
+      const char* o = (const char*)it->first;
+      if (o < lo + bytes && lo < o + it->second.bytes) {
+        busy = true;
+        it = c.holder.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    if (busy) HIP_TRY(hipDeviceSynchronize());
     rc = bind_plan(p, workspace, bytes);
     if (rc != TAMM_OK) return rc;
-    c.holder[workspace] = p;
+    c.holder[workspace] = ContractCache::Holder{p, bytes};
   }
   return tamm_plan_execute(p, alpha, beta, stream);
 }

@@ -46,13 +46,27 @@ class Problem:
 
 
 def max_rel(got_blocks, ref_blocks, keys=None):
+    """Parity metric over the given blocks (all of ``ref_blocks`` by default).
+
+    Returns ``(rel, max_abs)``: ``rel`` is the larger of the relative Frobenius error
+    ``||got - ref||_F / ||ref||_F`` and the element-wise error ``max |got - ref| / max |ref|``, so
+    a test asserting ``rel <= tol`` bounds every single element as well as the aggregate;
+    ``max_abs`` is ``max |got - ref|``.
+    """
     keys = list(ref_blocks.keys()) if keys is None else keys
     num = 0.0
     den = 0.0
     mx = 0.0
+    ref_mx = 0.0
     for k in keys:
         d = got_blocks[k] - ref_blocks[k]
+        if not np.all(np.isfinite(got_blocks[k])):
+            return float("inf"), float("inf")
         num += float(np.sum(d * d))
         den += float(np.sum(ref_blocks[k] * ref_blocks[k]))
-        mx = max(mx, float(np.max(np.abs(d))) if d.size else 0.0)
-    return (np.sqrt(num / den) if den > 0 else np.sqrt(num)), mx
+        if d.size:
+            mx = max(mx, float(np.max(np.abs(d))))
+            ref_mx = max(ref_mx, float(np.max(np.abs(ref_blocks[k]))))
+    frob = np.sqrt(num / den) if den > 0 else np.sqrt(num)
+    elem = mx / ref_mx if ref_mx > 0 else mx
+    return max(float(frob), float(elem)), mx

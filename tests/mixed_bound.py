@@ -1,0 +1,118 @@
+"""Element-wise error bounds of the mixed-precision contraction paths, derived from their definitions.
+
+For one output element r = sum_k a_k b_k (times alpha) the device result differs from the float64
+value by the operand rounding (f32) or the dropped split terms (bf16x3, bf16x4_aligned), plus the
+float32 rounding of the window sums, plus float64 rounding.  With u = 2^-24 (half a float32 ulp),
+u_mfma the relative error of one matrix-core accumulation step (its result rounded once; at most
+one float32 ulp, 2u), W = 256 the promotion window and n_w the windows of the element:
+
+  f32:    |err| <= (2u + u^2 + (W/4) u_mfma + n_w 2^-52) S
+          -- each operand rounded once (relative u); 64 chained 4-deep accumulation steps per
+          window, each rounded relative to a partial sum of magnitude <= S_window.
+  bf16x3: |err| <= (4.1 u + 8 (1+2^-7) u_mfma + 40 * 0.0079 u_mfma + n_w 2^-52) S
+          -- slices b_i = bf16(...) leave |x - b0 - b1 - b2| <= 2^-24 |x| and |b_i| <= 2^-8i |x|
+          (1 + 2^-8), so the dropped products (i + j >= 3, and the remainders) sum to < 4.1 u |ab|;
+          b0*b0 runs in its own accumulator (8 steps per window), the five products of order 1
+          and 2 (together <= 0.0079 |ab|) in another (40 steps per window).
+  bf16x4_aligned: |err| <= (1.2e-9 + 72 * 0.0079 u_mfma + n_w 2^-52) T
+          -- T = sum_k max_a max_b over the (row, window) maxima of |a| and |b|: the lead slices are
+          multiples of 2^(E-8) below a window maximum 2^(E-1) <= max < 2^E, their window sums are
+          exact in float32; the residual |x - lead| <= 2^-8 max is split in three bfloat16 slices
+          (remainder <= 2^-32 max); dropped products of order >= 4 and remainders < 5 * 2^-32;
+          the nine residual products (together <= 0.0079 max_a max_b) run 72 steps per window.
+
+S = sum_k |a_k| |b_k| is the same contraction on |lhs|, |rhs| (times |alpha|); T is it on operands
+whose elements are replaced by their (row, window) maximum magnitude, windows as the header of
+the library defines them (the flattening order of oracle.split).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from oracle import split as osplit
+
+U = 2.0 ** -24
+WINDOW = osplit.WINDOW
+
+
+def coefficient(precision: str, u_mfma: float, n_windows: int) -> float:
+    f64 = n_windows * 2.0 ** -52 + 2.0 ** -52
+    if precision == "f32":
+        return 2 * U + U * U + (WINDOW // 4) * u_mfma + f64
+    if precision == "bf16x3":
+        return 4.1 * U + 8 * (1 + 2.0 ** -7) * u_mfma + 40 * 0.0079 * u_mfma + f64
+    if precision == "bf16x4_aligned":
+        return 1.2e-9 + 72 * 0.0079 * u_mfma + f64
+    raise ValueError(precision)
+
+
+def window_max(block: np.ndarray, block_lbl: str, k_order: str) -> np.ndarray:
+    """Each element replaced by the largest magnitude of its (row, window) in the split layout."""
+    row_lbl = [c for c in block_lbl if c not in k_order]
+    perm = [block_lbl.index(c) for c in row_lbl] + [block_lbl.index(c) for c in k_order]
+    t = np.abs(np.transpose(block, perm))
+    rows = int(np.prod([t.shape[i] for i in range(len(row_lbl))], dtype=np.int64))
+    flat = t.reshape(rows, -1)
+    out = np.empty_like(flat)
+    for k0 in range(0, flat.shape[1], WINDOW):
+        w = flat[:, k0:k0 + WINDOW]
+        out[:, k0:k0 + WINDOW] = np.max(w, axis=1, keepdims=True) if w.size else 0.0
+    return np.transpose(out.reshape(t.shape), np.argsort(perm))
+
+
+class _Mapped(dict):
+    """Block dictionary applying ``fn`` to the blocks of another (lazily, cached)."""
+
+    def __init__(self, src, fn):
+        super().__init__()
+        self._src, self._fn = src, fn
+
+    def __missing__(self, key):
+        v = self._fn(key, self._src[key])
+        self[key] = v
+        return v
+
+
+def _mapped(t: oracle.BlockTensor, fn) -> oracle.BlockTensor:
+    x = oracle.BlockTensor(t.spaces, t.nonzero)
+    x.blocks = _Mapped(t.blocks, fn)
+    return x
+
+
+def bound_blocks(precision, out, ol, lhs, ll, rhs, rl, alpha, tiles, u_mfma):
+    """Per sampled output block the element-wise bound (same shape as the block)."""
+    k_order = osplit.summed_label_order(ol, ll, rl)
+    if precision == "bf16x4_aligned":
+        A = _mapped(lhs, lambda t, b: window_max(b, ll, k_order))
+        B = _mapped(rhs, lambda t, b: window_max(b, rl, k_order))
+    else:
+        A = _mapped(lhs, lambda t, b: np.abs(b))
+        B = _mapped(rhs, lambda t, b: np.abs(b))
+    mag = oracle.contract(out, ol, A, ll, B, rl, abs(alpha), 0.0, out_tiles=tiles).blocks
+    # windows per element: the summed extent of the element's surviving pairs, in windows
+    scr = oracle.screen(out, ol, lhs, ll, rhs, rl)
+    kl = [c for c in ll if c not in ol]
+    res = {}
+    for t in tiles:
+        nw = 0
+        for kt in scr["pairs"][t]:
+            ext = 1
+            for c, ti in zip(kl, kt):
+                ext *= lhs.spaces[ll.index(c)].sizes[ti]
+            nw += -(-ext // WINDOW)
+        res[t] = coefficient(precision, u_mfma, nw) * mag[t]
+    return res
+
+
+def check(got, ref, bound, keys):
+    """Largest ratio |got - ref| / bound over the sampled elements (must be <= 1)."""
+    worst = 0.0
+    for k in keys:
+        d = np.abs(got[k] - ref[k])
+        b = bound[k]
+        if np.any(d > b):
+            return float(np.max(d / np.maximum(b, 1e-300)))
+        worst = max(worst, float(np.max(d / np.maximum(b, 1e-300))))
+    return worst

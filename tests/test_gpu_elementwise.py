@@ -1,0 +1,114 @@
+"""SetOp and AddOp (Sec. III-A, Fig. 3 rules 5-7) on the GPU against the oracle, element by element.
+
+beta = 0 results are a single float64 product on both sides, so they must agree bit for bit;
+with beta != 0 the device may fuse beta*out + alpha*in into one rounding, so each element may
+differ from the oracle's two-rounding sum by at most one unit in the last place of the terms.
+"""
+
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2201_01257_amd import core as tm
+from tests.gpu_util import Problem
+
+pytestmark = pytest.mark.gpu
+
+
+def dense_pair(prob, pattern, seed):
+    rng = np.random.default_rng(seed)
+    g = tm.Tensor([prob.g[c] for c in pattern])
+    o = oracle.BlockTensor([prob.o[c] for c in pattern])
+    dense = rng.standard_normal(tuple(s.extent for s in o.spaces))
+    o = oracle.BlockTensor.from_dense(o.spaces, dense)
+    g.from_dense(dense)
+    return g, o
+
+
+def assert_add_close(got, ref, out0, inp, alpha, beta):
+    for t, r in ref.blocks.items():
+        g = got[t]
+        if beta == 0.0:
+            assert np.array_equal(g, r), t
+        else:
+            scale = np.abs(beta * out0.blocks[t]) + np.abs(alpha * r - beta * out0.blocks[t])
+            assert np.all(np.abs(g - r) <= 2.0 ** -52 * 2 * scale + 1e-300), t
+
+
+@pytest.mark.parametrize("in_lbl", ["abij", "baij", "abji", "baji", "ijab", "jiba", "aibj"])
+@pytest.mark.parametrize("beta", [0.0, 1.0, -0.5])
+def test_add_permutations_match_oracle(in_lbl, beta):
+    # ragged tiles (remainders) on both spaces; direct (same last label) and transposed paths
+    prob = Problem(14, 22, 4, 5)
+    pat = "".join("v" if c in "ab" else "o" for c in in_lbl)
+    out, out_o = dense_pair(prob, "vvoo", 1)
+    inp_g = tm.Tensor([prob.g[c] for c in pat])
+    inp_o = oracle.BlockTensor([prob.o[c] for c in pat])
+    rng = np.random.default_rng(2)
+    dense = rng.standard_normal(tuple(s.extent for s in inp_o.spaces))
+    inp_o = oracle.BlockTensor.from_dense(inp_o.spaces, dense)
+    inp_g.from_dense(dense)
+    alpha = -0.75
+    if beta == 0.0:  # "=" never reads out
+        out.data.fill_(float("nan"))
+    op = tm.Add(out, "abij", inp_g, in_lbl)
+    op.execute(alpha, beta)
+    torch.cuda.synchronize()
+    ref = oracle.add(out_o, "abij", inp_o, in_lbl, alpha, beta)
+    assert_add_close(out.to_blocks(), ref, out_o, inp_o, alpha, beta)
+
+
+def test_add_rank2_and_rank3_every_permutation():
+    prob = Problem(10, 18, 3, 4)
+    for pattern in ("vo", "vvo"):
+        letters = "abc"[:len(pattern)]
+        for perm in itertools.permutations(range(len(pattern))):
+            in_lbl = "".join(letters[p] for p in perm)
+            in_pat = "".join(pattern[p] for p in perm)
+            out, out_o = dense_pair(prob, pattern, 3)
+            inp, inp_o = dense_pair(prob, in_pat, 4)
+            tm.Add(out, letters, inp, in_lbl).execute(1.25, 1.0)
+            torch.cuda.synchronize()
+            ref = oracle.add(out_o, letters, inp_o, in_lbl, 1.25, 1.0)
+            assert_add_close(out.to_blocks(), ref, out_o, inp_o, 1.25, 1.0)
+
+
+def test_add_in_place_scale_and_overlap_rejected():
+    prob = Problem(12, 20, 6, 10)
+    x, x_o = dense_pair(prob, "vvoo", 5)
+    tm.Add(x, "abij", x, "abij").execute(-2.0, 0.0)
+    torch.cuda.synchronize()
+    ref = oracle.add(x_o, "abij", x_o, "abij", -2.0, 0.0)
+    assert all(np.array_equal(x.to_blocks()[t], r) for t, r in ref.blocks.items())
+    with pytest.raises(tm.TammError):
+        tm.Add(x, "abij", x, "abji").execute(1.0, 1.0)  # a permuted in-place add would race
+
+
+def test_set_value_every_stored_element():
+    prob = Problem(10, 26, 5, 6)
+    x, x_o = dense_pair(prob, "vvoo", 6)
+    tm.set_value(x, 0.375)
+    torch.cuda.synchronize()
+    ref = oracle.set_value(x_o, 0.375)
+    got = x.to_blocks()
+    assert all(np.array_equal(got[t], r) for t, r in ref.blocks.items())
+    y = tm.Tensor([prob.g["v"], prob.g["o"]])
+    # odd storage offset: the first element alone, then 16-byte pairs
+    buf = torch.full((y.numel + 1,), 7.0, dtype=torch.float64, device="cuda")
+    y.bind(buf[1:])
+    tm.set_value(y, -1.0)
+    torch.cuda.synchronize()
+    assert buf[0].item() == 7.0 and bool(torch.all(buf[1:] == -1.0))
+
+
+def test_add_label_errors():
+    prob = Problem(10, 18, 5, 6)
+    x = prob.gpu_tensor(None, "vvoo", fill=False)
+    y = prob.gpu_tensor(None, "vovo", fill=False)
+    with pytest.raises(tm.TammError):
+        tm.Add(x, "abij", x, "abik")
+    with pytest.raises(tm.TammError):
+        tm.Add(x, "abij", y, "abij")  # b binds o in y
