@@ -386,6 +386,63 @@ int tamm_add_execute(tamm_add* a, double alpha, double beta, void* stream);
 int tamm_add_destroy(tamm_add* a);
 
 /* ------------------------------------------------------------------------------------------
+ * Scheduler (Sec. III-A, Fig. 4: operations are queued on a scheduler and executed together;
+ * Sec. III-B: a dataflow analysis over the queued operations finds the conflicts -- two
+ * operations that share a tensor, at least one of them writing it -- and a levelized execution
+ * runs the non-conflicting operations of a level together).
+ *
+ * Queue operations (host only, in program order; nothing runs yet):
+ *   tamm_sched_set         SetOp          out = alpha on every stored element
+ *   tamm_sched_add         AddOp          out = beta*out + alpha*in(permuted), a prepared tamm_add
+ *   tamm_sched_contract    MultOp         out = beta*out + alpha*lhs*rhs, a float64 plan
+ *                                         (ERR_UNSUPPORTED for other precisions)
+ *   tamm_sched_denominator the denominator update of a prepared tamm_denominator; `energy` (rank
+ *                          device pointers, as for tamm_denominator_execute) is copied at queue
+ *                          time.
+ * The queued objects (plans, AddOps, denominators, their tensors) must outlive the schedule, and
+ * AddOps and denominators keep their own bound workspaces; plans' own workspaces are not used.
+ *
+ * tamm_sched_build (host only) analyses the queue once:
+ *   - fusion: a contraction with beta = 1 whose output was last touched by a contraction (or a
+ *     fused chain of them) with the same output tensor and the same alpha, whose plan splits the
+ *     output into the same rows and columns, and with no operation queued in between that writes
+ *     a tensor the chain reads, joins that chain: the chain is one node whose output tiles each
+ *     run one K loop over the pairs of every member (same-output fusion).  Members must share
+ *     alpha; a term whose coefficient differs is fused by scaling one of its operands upstream.
+ *   - levels: nodes, in the order of their last queued operation, each go one level after the
+ *     latest earlier node they conflict with (tensors compared by handle and by storage overlap).
+ *   Every level runs as one group launch of its contraction nodes (screening, one persistent
+ *   contraction launch per gather layout class) followed by its element-wise operations; the
+ *   result equals running the queue in program order.
+ * tamm_sched_workspace_size / _bind_workspace: one caller-owned device workspace (256-byte
+ *   aligned) for every level's group, sized so that the autotuner's candidates fit; binding
+ *   copies the static tables in (synchronous).
+ * tamm_sched_autotune: the group autotuner (tamm_group_autotune) on every level (outputs left
+ *   unchanged for finite inputs; synchronises the stream).
+ * tamm_sched_execute: enqueue every level on stream.  If a graph was captured and every tensor
+ *   and energy array is still bound to the same storage, the graph is replayed; otherwise the
+ *   launches are issued directly (descriptor refreshes synchronise the stream when bindings moved).
+ * tamm_sched_capture: record the whole schedule into one hipGraph (no memset or copy nodes).
+ * tamm_sched_info: levels, nodes, and operations inside fused nodes; tamm_sched_op_info: level and
+ *   node of queued operation `op` (0-based, queue order).
+ * ------------------------------------------------------------------------------------------ */
+typedef struct tamm_sched tamm_sched;
+int tamm_sched_create(tamm_sched** s);
+int tamm_sched_set(tamm_sched* s, tamm_tensor* out, double alpha);
+int tamm_sched_add(tamm_sched* s, tamm_add* a, double alpha, double beta);
+int tamm_sched_contract(tamm_sched* s, tamm_plan* p, double alpha, double beta);
+int tamm_sched_denominator(tamm_sched* s, tamm_denominator* d, const double* const* energy);
+int tamm_sched_build(tamm_sched* s);
+int tamm_sched_workspace_size(const tamm_sched* s, size_t* bytes);
+int tamm_sched_bind_workspace(tamm_sched* s, void* workspace, size_t bytes);
+int tamm_sched_autotune(tamm_sched* s, void* stream, const char* cache_path, int32_t reps);
+int tamm_sched_execute(tamm_sched* s, void* stream);
+int tamm_sched_capture(tamm_sched* s, void* stream);
+int tamm_sched_info(const tamm_sched* s, int32_t* levels, int32_t* nodes, int32_t* fused_ops);
+int tamm_sched_op_info(const tamm_sched* s, int32_t op, int32_t* level, int32_t* node);
+int tamm_sched_destroy(tamm_sched* s);
+
+/* ------------------------------------------------------------------------------------------
  * Diagnostic: execute one matrix-core instruction on one wave with caller data (device
  * pointers, enqueued on stream), for tests of its lane layout and of the rounding of its float32
  * accumulation on inputs whose exact results are known.  The contraction path never calls it.

@@ -88,6 +88,20 @@ SIGNATURES = {
     "tamm_add_execute": (c_int, [c_vp, c_dbl, c_dbl, c_vp]),
     "tamm_add_destroy": (c_int, [c_vp]),
     "tamm_diag_mfma": (c_int, [c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "tamm_sched_create": (c_int, [P(c_vp)]),
+    "tamm_sched_set": (c_int, [c_vp, c_vp, c_dbl]),
+    "tamm_sched_add": (c_int, [c_vp, c_vp, c_dbl, c_dbl]),
+    "tamm_sched_contract": (c_int, [c_vp, c_vp, c_dbl, c_dbl]),
+    "tamm_sched_denominator": (c_int, [c_vp, c_vp, P(c_vp)]),
+    "tamm_sched_build": (c_int, [c_vp]),
+    "tamm_sched_workspace_size": (c_int, [c_vp, P(c_size_t)]),
+    "tamm_sched_bind_workspace": (c_int, [c_vp, c_vp, c_size_t]),
+    "tamm_sched_autotune": (c_int, [c_vp, c_vp, c_char_p, c_i32]),
+    "tamm_sched_execute": (c_int, [c_vp, c_vp]),
+    "tamm_sched_capture": (c_int, [c_vp, c_vp]),
+    "tamm_sched_info": (c_int, [c_vp, P(c_i32), P(c_i32), P(c_i32)]),
+    "tamm_sched_op_info": (c_int, [c_vp, c_i32, P(c_i32), P(c_i32)]),
+    "tamm_sched_destroy": (c_int, [c_vp]),
 }
 
 STATUS = {

@@ -427,6 +427,83 @@ class Add:
         _d(self, "tamm_add_destroy")
 
 
+class Scheduler:
+    """Queue of SetOp / AddOp / MultOp / denominator operations, analysed once into fused nodes and
+    dataflow levels and executed level by level (tamm_sched_*).  Keeps every queued object alive."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        check(load().tamm_sched_create(ctypes.byref(h)))
+        self._h = h
+        self._keep = []
+        self._ws = None
+        self.n_ops = 0
+
+    def set(self, out: Tensor, alpha: float):
+        check(load().tamm_sched_set(self._h, out._h, float(alpha)))
+        self._keep.append(out)
+        self.n_ops += 1
+        return self
+
+    def add(self, op: "Add", alpha: float = 1.0, beta: float = 0.0):
+        check(load().tamm_sched_add(self._h, op._h, float(alpha), float(beta)))
+        self._keep.append(op)
+        self.n_ops += 1
+        return self
+
+    def contract(self, plan: Plan, alpha: float = 1.0, beta: float = 0.0):
+        check(load().tamm_sched_contract(self._h, plan._h, float(alpha), float(beta)))
+        self._keep.append(plan)
+        self.n_ops += 1
+        return self
+
+    def denominator(self, den: "Denominator"):
+        check(load().tamm_sched_denominator(self._h, den._h, den._eptr))
+        self._keep.append(den)
+        self.n_ops += 1
+        return self
+
+    def build(self):
+        check(load().tamm_sched_build(self._h))
+        return self
+
+    def workspace_size(self) -> int:
+        n = ctypes.c_size_t()
+        check(load().tamm_sched_workspace_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    def bind_workspace(self, device="cuda"):
+        n = self.workspace_size()
+        self._ws, ptr = _aligned_workspace(n, device)
+        check(load().tamm_sched_bind_workspace(self._h, ctypes.c_void_p(ptr), n))
+        return self
+
+    def autotune(self, cache_path: str = "", reps: int = 2, stream=None):
+        s = current_stream_handle() if stream is None else stream
+        check(load().tamm_sched_autotune(self._h, s, cache_path.encode(), reps))
+
+    def execute(self, stream=None):
+        s = current_stream_handle() if stream is None else stream
+        check(load().tamm_sched_execute(self._h, s))
+
+    def capture(self, stream=None):
+        s = current_stream_handle() if stream is None else stream
+        check(load().tamm_sched_capture(self._h, s))
+
+    def info(self) -> dict:
+        lv, nd, fu = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(load().tamm_sched_info(self._h, ctypes.byref(lv), ctypes.byref(nd), ctypes.byref(fu)))
+        return {"levels": lv.value, "nodes": nd.value, "fused_ops": fu.value}
+
+    def op_info(self, i: int):
+        lv, nd = ctypes.c_int32(), ctypes.c_int32()
+        check(load().tamm_sched_op_info(self._h, i, ctypes.byref(lv), ctypes.byref(nd)))
+        return lv.value, nd.value
+
+    def __del__(self, _d=_destroy):
+        _d(self, "tamm_sched_destroy")
+
+
 class Group:
     """Independent float64 plans executed as one grouped persistent launch (optionally a hipGraph)."""
 
@@ -497,4 +574,4 @@ class Group:
         _d(self, "tamm_group_destroy")
 
 
-__all__ = ["Space", "Tensor", "Plan", "Group", "contract", "Denominator", "Add", "set_value", "TammError", "PRECISIONS"]
+__all__ = ["Space", "Tensor", "Plan", "Group", "contract", "Denominator", "Add", "set_value", "Scheduler", "TammError", "PRECISIONS"]

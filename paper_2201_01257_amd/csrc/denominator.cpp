@@ -89,7 +89,12 @@ extern "C" int tamm_denominator_bind_workspace(tamm_denominator* d, void* worksp
   return ok();
 }
 
-extern "C" int tamm_denominator_execute(tamm_denominator* d, const double* const* energy, void* stream) {
+void tamm::denominator_io(const tamm_denominator* d, tamm_tensor** out, const tamm_tensor** in) {
+  *out = d->out;
+  *in = d->in;
+}
+
+int tamm::denominator_enqueue(tamm_denominator* d, const double* const* energy, hipStream_t stream) {
   if (!d || !energy) return fail(TAMM_ERR_ARG, "null argument");
   if (!d->bound) return fail(TAMM_ERR_UNBOUND, "denominator workspace is not bound");
   if (!d->out->bound || !d->in->bound) return fail(TAMM_ERR_UNBOUND, "tensor storage not bound");
@@ -101,7 +106,7 @@ extern "C" int tamm_denominator_execute(tamm_denominator* d, const double* const
     dp.energy[k] = energy[k];
     dp.sign[k] = d->sign[k];
   }
-  if (d->item_block.empty()) return ok();
+  if (d->item_block.empty()) return TAMM_OK;
   dp.out = d->out->dev;
   dp.in = d->in->dev;
   dp.block_off = (const int64_t*)(d->ws + d->off_boff);
@@ -113,8 +118,13 @@ extern "C" int tamm_denominator_execute(tamm_denominator* d, const double* const
   dp.rank = t->rank;
   dp.chunk = d->chunk;
   dp.n_items = (int64_t)d->item_block.size();
-  HIP_TRY(launch_denominator(dp, (hipStream_t)stream));
-  return ok();
+  HIP_TRY(launch_denominator(dp, stream));
+  return TAMM_OK;
+}
+
+extern "C" int tamm_denominator_execute(tamm_denominator* d, const double* const* energy, void* stream) {
+  const int rc = denominator_enqueue(d, energy, (hipStream_t)stream);
+  return rc == TAMM_OK ? ok() : rc;
 }
 
 extern "C" int tamm_denominator_destroy(tamm_denominator* d) {

@@ -24,6 +24,23 @@ int add_enqueue(tamm_add* a, double alpha, double beta, hipStream_t s);
 const tamm_tensor* add_out(const tamm_add* a);
 const tamm_tensor* add_in(const tamm_add* a);
 
+// Plans and groups (plan.cpp), shared with the scheduler.
+void plan_io(const tamm_plan* p, tamm_tensor** out, const tamm_tensor** lhs, const tamm_tensor** rhs, int* precision);
+bool plans_fusable(tamm_plan* a, tamm_plan* b);
+int group_create_nodes(const std::vector<std::vector<tamm_plan*>>& nodes, tamm_group** out);
+int group_enqueue(tamm_group* g, hipStream_t s);
+int group_update_desc(tamm_group* g, const double* alpha, const double* beta, hipStream_t s, bool* changed);
+int group_check_bound(tamm_group* g);
+int group_autotune(tamm_group* g, hipStream_t s, const char* cache_path, int32_t reps);
+size_t group_workspace_size(const tamm_group* g);
+size_t group_autotune_workspace_size(tamm_group* g);
+int group_bind_ws(tamm_group* g, void* ws, size_t bytes);
+size_t group_node_count(const tamm_group* g);
+
+// Denominator update (denominator.cpp), shared with the scheduler.
+int denominator_enqueue(tamm_denominator* d, const double* const* energy, hipStream_t s);
+void denominator_io(const tamm_denominator* d, tamm_tensor** out, const tamm_tensor** in);
+
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SpaceData {

@@ -95,13 +95,23 @@ struct ContractParams {
   int32_t pad;
 };
 
+// Screening of one contraction (a segment).  Several contractions that write the same output
+// tiles (a fused node) screen as consecutive segments of one list: every segment appends its
+// surviving pairs to the pair list of the first segment's output block, with its operand element
+// offsets and table starts shifted so that they are relative to the first segment's operand base
+// pointers and table pool.
 struct ScreenDesc {
   const int64_t* a_tile_off;  // per A tile-linear index: element offset, -1 = not stored
   const int64_t* b_tile_off;
   const OutBlockDesc* blocks;
-  PairDesc* pairs;
-  int32_t* counts;            // surviving pairs per output block
-  const int32_t* pool;        // int32 table pool
+  PairDesc* pairs;            // pair list base (first segment's): block ob's pairs at ob * pair_stride
+  int32_t* counts;            // surviving pairs per output block (first segment's)
+  const int32_t* pool;        // this segment's int32 table pool
+  int64_t a_base;             // added to the A block offsets of the pairs (elements)
+  int64_t b_base;             // added to the B block offsets
+  int32_t pool_base;          // added to the table starts of the pairs (int32 entries)
+  int32_t pair_stride;        // pair capacity per output block
+  int32_t next_seg;           // index of the next segment in ScreenParams::probs, -1: last
   int32_t n_blocks;
   int32_t n_kt;               // K tile tuples (pair capacity per output block)
   int32_t nk;                 // number of K labels

@@ -13,54 +13,62 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------------------------
 // Tile-pair screening (the block non-zero analysis).  One wave per stored output block walks the
 // K tile tuples in lexicographic order, keeps a pair when both operand blocks are stored, and
-// compacts the survivors in order with a wave ballot (deterministic, no atomics).
+// compacts the survivors in order with a wave ballot (deterministic, no atomics).  A fused node
+// (several contractions into the same output tiles) walks its segments one after another and
+// appends to one list, so that one output tile's K loop later runs over every segment's pairs.
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_screen(ScreenParams P) {
   const int item = blockIdx.x;
   if (item >= P.n_items) return;
-  const ScreenDesc& S = P.probs ? P.probs[P.item_prob[item]] : P.single;
+  const ScreenDesc* S = P.probs ? P.probs + P.item_prob[item] : &P.single;
   const int ob = P.probs ? P.item_block[item] : item;
   const int lane = threadIdx.x;
-  const OutBlockDesc blk = S.blocks[ob];
+  PairDesc* __restrict__ out = S->pairs + (int64_t)ob * S->pair_stride;
+  int32_t* counts = S->counts;
   int count = 0;
-  for (int kt0 = 0; kt0 < S.n_kt; kt0 += 64) {
-    const int kt = kt0 + lane;
-    bool keep = false;
-    int64_t aoff = -1, boff = -1;
-    int kext = 1, acls = blk.a_cbase, bcls = blk.b_cbase;
-    if (kt < S.n_kt) {
-      int rem = kt, alin = blk.a_tbase, blin = blk.b_tbase;
-      for (int k = S.nk - 1; k >= 0; --k) {
-        const int t = rem % S.k_ntiles[k];
-        rem /= S.k_ntiles[k];
-        alin += t * S.a_tstride[k];
-        blin += t * S.b_tstride[k];
-        const int c = S.pool[S.k_cls_tab[k] + t];
-        acls += c * S.a_cstride[k];
-        bcls += c * S.b_cstride[k];
-        kext *= S.pool[S.k_size_tab[k] + t];
+  while (true) {  // segments of a fused node append to one list, in order
+    const OutBlockDesc blk = S->blocks[ob];
+    for (int kt0 = 0; kt0 < S->n_kt; kt0 += 64) {
+      const int kt = kt0 + lane;
+      bool keep = false;
+      int64_t aoff = -1, boff = -1;
+      int kext = 1, acls = blk.a_cbase, bcls = blk.b_cbase;
+      if (kt < S->n_kt) {
+        int rem = kt, alin = blk.a_tbase, blin = blk.b_tbase;
+        for (int k = S->nk - 1; k >= 0; --k) {
+          const int t = rem % S->k_ntiles[k];
+          rem /= S->k_ntiles[k];
+          alin += t * S->a_tstride[k];
+          blin += t * S->b_tstride[k];
+          const int c = S->pool[S->k_cls_tab[k] + t];
+          acls += c * S->a_cstride[k];
+          bcls += c * S->b_cstride[k];
+          kext *= S->pool[S->k_size_tab[k] + t];
+        }
+        aoff = S->a_tile_off[alin];
+        boff = S->b_tile_off[blin];
+        keep = aoff >= 0 && boff >= 0;
       }
-      aoff = S.a_tile_off[alin];
-      boff = S.b_tile_off[blin];
-      keep = aoff >= 0 && boff >= 0;
+      const unsigned long long mask = __ballot(keep);
+      if (keep) {
+        const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+        PairDesc d;
+        d.a_off = aoff + S->a_base;
+        d.b_off = boff + S->b_base;
+        d.kext = kext;
+        d.a_tabM = S->pool[S->a_cls_tabM + acls] + S->pool_base;
+        d.a_tabK = S->pool[S->a_cls_tabK + acls] + S->pool_base;
+        d.b_tabK = S->pool[S->b_cls_tabK + bcls] + S->pool_base;
+        d.b_tabN = S->pool[S->b_cls_tabN + bcls] + S->pool_base;
+        d.kt = kt;
+        out[count + rank] = d;
+      }
+      count += __popcll(mask);
     }
-    const unsigned long long mask = __ballot(keep);
-    if (keep) {
-      const int rank = __popcll(mask & ((1ull << lane) - 1ull));
-      PairDesc d;
-      d.a_off = aoff;
-      d.b_off = boff;
-      d.kext = kext;
-      d.a_tabM = S.pool[S.a_cls_tabM + acls];
-      d.a_tabK = S.pool[S.a_cls_tabK + acls];
-      d.b_tabK = S.pool[S.b_cls_tabK + bcls];
-      d.b_tabN = S.pool[S.b_cls_tabN + bcls];
-      d.kt = kt;
-      S.pairs[blk.pair_base + count + rank] = d;
-    }
-    count += __popcll(mask);
+    if (S->next_seg < 0) break;
+    S = P.probs + S->next_seg;
   }
-  if (lane == 0) S.counts[ob] = count;
+  if (lane == 0) counts[ob] = count;
 }
 
 hipError_t launch_screen(const ScreenParams& p, hipStream_t s) {

@@ -169,6 +169,11 @@ static ScreenDesc screen_desc(const tamm_plan* p, char* ws, const Layout& L) {
   s.pairs = (PairDesc*)(ws + L.pairs);
   s.counts = (int32_t*)(ws + L.counts);
   s.pool = (const int32_t*)(ws + L.pool);
+  s.a_base = 0;
+  s.b_base = 0;
+  s.pool_base = 0;
+  s.pair_stride = (int32_t)p->n_kt;
+  s.next_seg = -1;
   s.n_blocks = (int32_t)p->blocks.size();
   return s;
 }
@@ -1134,16 +1139,25 @@ extern "C" int tamm_plan_autotune(tamm_plan* p, void* workspace, size_t bytes, v
 }
 
 // ---------------------------------------------------------------------------------------------
-// groups: many independent plans, one screening launch and one persistent contraction launch per
-// gather layout class (each with its own configuration), optionally captured once into a hipGraph
-// and replayed.
+// groups: contraction nodes executed together -- one screening launch and one persistent
+// contraction launch per gather layout class (each with its own configuration), optionally
+// captured once into a hipGraph and replayed.  A node is one plan, or several plans that write
+// the same output tiles (a fused node, built by the scheduler): their pair lists are screened
+// into one list per output block and one output tile's K loop runs over all of them.
 // ---------------------------------------------------------------------------------------------
 struct tamm_group {
-  std::vector<tamm_plan*> plans;
-  std::vector<Layout> lays;
+  std::vector<std::vector<tamm_plan*>> nodes;  // member plans of each node
+  std::vector<tamm_plan*> plans;               // every member plan, node by node
+  std::vector<int32_t> node_first;             // index in `plans` (and segment index) of each node's first plan
+  std::vector<Layout> lays;                    // static tables of each plan
+  struct Fused {
+    size_t blocks = 0, pairs = 0, counts = 0;  // regions of a fused node's own output descriptors and pair list
+    int32_t stride = 0;                        // pair capacity per output block (sum over the members)
+  };
+  std::vector<Fused> fused;                    // per node (fused nodes only)
   size_t off_sdesc = 0, off_pdesc = 0, off_sitems = 0, off_work = 0, off_counter = 0, ws_size = 0;
-  std::vector<int32_t> sitem_prob, sitem_block;
-  std::vector<WorkItem> work;       // grouped by gather layout class, each class longest first
+  std::vector<int32_t> sitem_prob, sitem_block;  // screening items: first segment of the node, output block
+  std::vector<WorkItem> work;       // grouped by gather layout class, each class longest first (prob = node)
   size_t work_capacity = 0;         // work items of the largest mix of per-class configurations
   int32_t cls_begin[kLayouts + 1] = {};  // work range of gather layout c: [cls_begin[c], cls_begin[c+1])
   int cfg[kLayouts] = {};   // kernel configuration of each layout class (its tile shape)
@@ -1152,7 +1166,8 @@ struct tamm_group {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   bool bound = false;
-  std::vector<ProblemDesc> pdesc;   // host copy (alpha/beta updated per execute)
+  std::vector<ProblemDesc> pdesc;   // host copy per node (alpha/beta updated per execute)
+  std::vector<ScreenDesc> sdesc;    // host copy per plan (segment)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<double> g_alpha, g_beta;
@@ -1165,7 +1180,23 @@ static void group_drop_graph(tamm_group* g) {
   g->graph = nullptr;
 }
 
-// Default configuration of a set of members: the one with the least padding, ties to the larger
+// Gather layout of a node: its plans share the operand orientations; 16-byte gathers only when
+// every member's tables allow them.
+static int node_layout(const tamm_group* g, size_t q) {
+  int lay = gather_layout(g->nodes[q][0]) & 3;
+  bool pairs = true;
+  for (const tamm_plan* p : g->nodes[q]) pairs = pairs && p->pairs;
+  return lay | (pairs ? 4 : 0);
+}
+
+// Summed K extent of the surviving pairs of output block b over the node's plans.
+static double node_block_cost(const tamm_group* g, size_t q, size_t b) {
+  double c = 0;
+  for (const tamm_plan* p : g->nodes[q]) c += p->block_cost[b];
+  return c;
+}
+
+// Default configuration of a set of nodes: the one with the least padding, ties to the larger
 // tile.
 static int group_default_config(const tamm_group* g, int layout) {
   int config = 0;
@@ -1174,9 +1205,9 @@ static int group_default_config(const tamm_group* g, int layout) {
     const F64Config& f = f64_config(c);
     if (f.kt != 16 || f.wgm * f.wgn != 4 || f.mt > 128 || f.nt > 128) continue;
     double area = 0, useful = 0;
-    for (auto* p : g->plans) {
-      if (layout >= 0 && gather_layout(p) != layout) continue;
-      for (const auto& b : p->blocks) {
+    for (size_t q = 0; q < g->nodes.size(); ++q) {
+      if (layout >= 0 && node_layout(g, q) != layout) continue;
+      for (const auto& b : g->nodes[q][0]->blocks) {
         area += (double)((b.mext + f.mt - 1) / f.mt) * f.mt * ((b.next + f.nt - 1) / f.nt) * f.nt;
         useful += (double)b.mext * b.next;
       }
@@ -1191,7 +1222,7 @@ static int group_default_config(const tamm_group* g, int layout) {
 }
 
 // Work lists of every layout class with the class's configuration cfgs[c] (< 0: the class's
-// default), each heaviest first.
+// default), each heaviest first, and the workspace layout.
 static int group_configure_classes(tamm_group* g, const int* cfgs) {
   for (int c = 0; c < kLayouts; ++c) {
     const int k = cfgs[c] < 0 ? group_default_config(g, c) : cfgs[c];
@@ -1206,15 +1237,16 @@ static int group_configure_classes(tamm_group* g, const int* cfgs) {
   for (int c = 0; c < kLayouts; ++c) {
     const F64Config& f = f64_config(g->cfg[c]);
     std::vector<Tile> tiles;
-    for (size_t q = 0; q < g->plans.size(); ++q) {
-      const tamm_plan* p = g->plans[q];
-      if (gather_layout(p) != c) continue;
+    for (size_t q = 0; q < g->nodes.size(); ++q) {
+      if (node_layout(g, q) != c) continue;
+      const tamm_plan* p = g->nodes[q][0];
       int32_t t = 0;
       for (size_t b = 0; b < p->blocks.size(); ++b) {
         const auto& d = p->blocks[b];
+        const double bc = node_block_cost(g, q, b);
         for (int32_t m0 = 0; m0 < d.mext; m0 += f.mt)
           for (int32_t n0 = 0; n0 < d.next; n0 += f.nt)
-            tiles.push_back(Tile{p->block_cost[b] * std::min(f.mt, d.mext - m0) * std::min(f.nt, d.next - n0),
+            tiles.push_back(Tile{bc * std::min(f.mt, d.mext - m0) * std::min(f.nt, d.next - n0),
                                  WorkItem{(int32_t)q, (int32_t)b, m0, n0, 0, t++}});
       }
     }
@@ -1229,10 +1261,25 @@ static int group_configure_classes(tamm_group* g, const int* cfgs) {
     g->lays.push_back(make_layout(p, off));
     off = g->lays.back().end;
   }
+  g->fused.assign(g->nodes.size(), tamm_group::Fused{});
+  for (size_t q = 0; q < g->nodes.size(); ++q) {
+    if (g->nodes[q].size() < 2) continue;
+    tamm_group::Fused& F = g->fused[q];
+    const size_t nob = g->nodes[q][0]->blocks.size();
+    int64_t stride = 0;
+    for (const tamm_plan* p : g->nodes[q]) stride += p->n_kt;
+    F.stride = (int32_t)stride;
+    F.blocks = align256(off);
+    off = align256(F.blocks + nob * sizeof(OutBlockDesc));
+    F.pairs = off;
+    off = align256(off + nob * (size_t)stride * sizeof(PairDesc));
+    F.counts = off;
+    off = align256(off + nob * sizeof(int32_t));
+  }
   g->off_sdesc = off;
   off = align256(off + g->plans.size() * sizeof(ScreenDesc));
   g->off_pdesc = off;
-  off = align256(off + g->plans.size() * sizeof(ProblemDesc));
+  off = align256(off + g->nodes.size() * sizeof(ProblemDesc));
   g->off_sitems = off;
   off = align256(off + g->sitem_prob.size() * 2 * sizeof(int32_t));
   g->off_work = off;
@@ -1254,21 +1301,57 @@ static int group_configure(tamm_group* g, int config) {
   return group_configure_classes(g, cfgs);
 }
 
-extern "C" int tamm_group_create(tamm_plan* const* plans, int32_t n, tamm_group** out) {
-  if (!out) return fail(TAMM_ERR_ARG, "null output pointer");
+// Plans that can share output tiles: float64, the same output tensor, the same flattening of the
+// output's labels into rows (M) and columns (N), and the same operand orientations.
+static int check_fusable(const std::vector<tamm_plan*>& node) {
+  const tamm_plan* p0 = node[0];
+  auto out_dims = [](const tamm_plan* p, const std::vector<int>& grp) {
+    std::vector<int> d;
+    for (int l : grp) d.push_back(p->labels[l].od);
+    return d;
+  };
+  for (size_t i = 1; i < node.size(); ++i) {
+    const tamm_plan* p = node[i];
+    if (p->out != p0->out) return fail(TAMM_ERR_ARG, "fused plans must write the same output tensor");
+    if (out_dims(p, p->M) != out_dims(p0, p0->M) || out_dims(p, p->N) != out_dims(p0, p0->N) || p->a_kc != p0->a_kc ||
+        p->b_kc != p0->b_kc)
+      return fail(TAMM_ERR_UNSUPPORTED, "fused plans must split the output into the same rows and columns");
+  }
+  int64_t stride = 0;
+  for (const tamm_plan* p : node) stride += p->n_kt;
+  if ((int64_t)p0->blocks.size() * stride > (int64_t)1 << 28) return fail(TAMM_ERR_UNSUPPORTED, "fused pair capacity too large");
+  return TAMM_OK;
+}
+
+namespace tamm {
+
+// Create a group of nodes (each node one plan, or several fusable plans writing the same output).
+int group_create_nodes(const std::vector<std::vector<tamm_plan*>>& nodes, tamm_group** out) {
   *out = nullptr;
-  if (!plans || n <= 0) return fail(TAMM_ERR_ARG, "a group needs at least one plan");
+  if (nodes.empty()) return fail(TAMM_ERR_ARG, "a group needs at least one plan");
   auto g = std::make_unique<tamm_group>();
   uint64_t h = 0xCBF29CE484222325ULL;
-  for (int32_t i = 0; i < n; ++i) {
-    if (!plans[i]) return fail(TAMM_ERR_ARG, "plan %d is null", i);
-    if (plans[i]->prec != TAMM_PREC_F64) return fail(TAMM_ERR_UNSUPPORTED, "groups run float64 plans only");
-    for (int32_t j = 0; j < i; ++j)
-      if (plans[j]->out == plans[i]->out) return fail(TAMM_ERR_ARG, "plans %d and %d write the same output tensor", j, i);
-    g->plans.push_back(plans[i]);
-    h = fnv(h, &plans[i]->signature, sizeof(uint64_t));
-    for (size_t b = 0; b < plans[i]->blocks.size(); ++b) {
-      g->sitem_prob.push_back(i);
+  for (size_t q = 0; q < nodes.size(); ++q) {
+    if (nodes[q].empty()) return fail(TAMM_ERR_ARG, "node %zu is empty", q);
+    for (tamm_plan* p : nodes[q]) {
+      if (!p) return fail(TAMM_ERR_ARG, "a member plan is null");
+      if (p->prec != TAMM_PREC_F64) return fail(TAMM_ERR_UNSUPPORTED, "groups run float64 plans only");
+    }
+    int rc = check_fusable(nodes[q]);
+    if (rc != TAMM_OK) return rc;
+    for (size_t r = 0; r < q; ++r)
+      if (nodes[r][0]->out == nodes[q][0]->out)
+        return fail(TAMM_ERR_ARG, "members %zu and %zu write the same output tensor", r, q);
+    g->nodes.push_back(nodes[q]);
+    g->node_first.push_back((int32_t)g->plans.size());
+    const uint32_t sz = (uint32_t)nodes[q].size();
+    h = fnv(h, &sz, sizeof(sz));
+    for (tamm_plan* p : nodes[q]) {
+      g->plans.push_back(p);
+      h = fnv(h, &p->signature, sizeof(uint64_t));
+    }
+    for (size_t b = 0; b < nodes[q][0]->blocks.size(); ++b) {
+      g->sitem_prob.push_back(g->node_first.back());
       g->sitem_block.push_back((int32_t)b);
     }
   }
@@ -1278,9 +1361,10 @@ extern "C" int tamm_group_create(tamm_plan* const* plans, int32_t n, tamm_group*
     for (int k = 0; k < f64_config_count(); ++k) {
       const F64Config& f = f64_config(k);
       size_t n = 0;
-      for (auto* p : g->plans)
-        if (gather_layout(p) == c)
-          for (const auto& b : p->blocks) n += (size_t)((b.mext + f.mt - 1) / f.mt) * ((b.next + f.nt - 1) / f.nt);
+      for (size_t q = 0; q < g->nodes.size(); ++q)
+        if (node_layout(g.get(), q) == c)
+          for (const auto& b : g->nodes[q][0]->blocks)
+            n += (size_t)((b.mext + f.mt - 1) / f.mt) * ((b.next + f.nt - 1) / f.nt);
       most = std::max(most, n);
     }
     g->work_capacity += most;
@@ -1288,7 +1372,22 @@ extern "C" int tamm_group_create(tamm_plan* const* plans, int32_t n, tamm_group*
   const int rc = group_configure(g.get(), -1);
   if (rc != TAMM_OK) return rc;
   *out = g.release();
-  return ok();
+  return TAMM_OK;
+}
+
+}  // namespace tamm
+
+extern "C" int tamm_group_create(tamm_plan* const* plans, int32_t n, tamm_group** out) {
+  if (!out) return fail(TAMM_ERR_ARG, "null output pointer");
+  *out = nullptr;
+  if (!plans || n <= 0) return fail(TAMM_ERR_ARG, "a group needs at least one plan");
+  std::vector<std::vector<tamm_plan*>> nodes;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!plans[i]) return fail(TAMM_ERR_ARG, "plan %d is null", i);
+    nodes.push_back({plans[i]});
+  }
+  const int rc = group_create_nodes(nodes, out);
+  return rc == TAMM_OK ? ok() : rc;
 }
 
 extern "C" int tamm_group_workspace_size(const tamm_group* g, size_t* bytes) {
@@ -1297,19 +1396,61 @@ extern "C" int tamm_group_workspace_size(const tamm_group* g, size_t* bytes) {
   return ok();
 }
 
+// Screening descriptors of every plan (segment) and problem descriptors of every node for the
+// current tensor bindings and coefficients.
+static void group_descs(const tamm_group* g, char* ws, const double* alpha, const double* beta, std::vector<ScreenDesc>& sds,
+                        std::vector<ProblemDesc>& pds) {
+  sds.clear();
+  pds.clear();
+  for (size_t q = 0; q < g->nodes.size(); ++q) {
+    const int first = g->node_first[q];
+    const tamm_plan* p0 = g->nodes[q][0];
+    const Layout& L0 = g->lays[first];
+    ProblemDesc pd = problem_desc(p0, ws, L0, nullptr, 1, alpha[q], beta[q]);
+    const bool fused = g->nodes[q].size() > 1;
+    const tamm_group::Fused& F = g->fused[q];
+    if (fused) {
+      pd.blocks = (const OutBlockDesc*)(ws + F.blocks);
+      pd.pairs = (const PairDesc*)(ws + F.pairs);
+      pd.counts = (const int32_t*)(ws + F.counts);
+    }
+    pds.push_back(pd);
+    for (size_t i = 0; i < g->nodes[q].size(); ++i) {
+      const tamm_plan* p = g->nodes[q][i];
+      const Layout& L = g->lays[first + i];
+      ScreenDesc s = screen_desc(p, ws, L);
+      if (fused) {
+        s.pairs = (PairDesc*)(ws + F.pairs);
+        s.counts = (int32_t*)(ws + F.counts);
+        s.pair_stride = F.stride;
+        // element offsets and table starts relative to the first member's operands and pool
+        s.a_base = (int64_t)((const double*)p->A->dev - (const double*)p0->A->dev);
+        s.b_base = (int64_t)((const double*)p->B->dev - (const double*)p0->B->dev);
+        s.pool_base = (int32_t)(((int64_t)L.pool - (int64_t)L0.pool) / (int64_t)sizeof(int32_t));
+        s.next_seg = i + 1 < g->nodes[q].size() ? first + (int32_t)i + 1 : -1;
+      }
+      sds.push_back(s);
+    }
+  }
+}
+
 static int group_bind(tamm_group* g, void* dev_ptr, size_t bytes) {
   if (!dev_ptr || ((uintptr_t)dev_ptr) % 256) return fail(TAMM_ERR_WORKSPACE, "workspace must be non-null and 256-byte aligned");
   if (bytes < g->ws_size) return fail(TAMM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", bytes, g->ws_size);
   char* ws = (char*)dev_ptr;
-  std::vector<ScreenDesc> sds;
-  g->pdesc.clear();
   for (size_t q = 0; q < g->plans.size(); ++q) {
     int rc = upload_static(g->plans[q], ws, g->lays[q]);
     if (rc != TAMM_OK) return rc;
-    sds.push_back(screen_desc(g->plans[q], ws, g->lays[q]));
-    g->pdesc.push_back(problem_desc(g->plans[q], ws, g->lays[q], nullptr, 1, 1.0, 0.0));
   }
-  HIP_TRY(hipMemcpy(ws + g->off_sdesc, sds.data(), sds.size() * sizeof(ScreenDesc), hipMemcpyHostToDevice));
+  for (size_t q = 0; q < g->nodes.size(); ++q) {
+    if (g->nodes[q].size() < 2) continue;
+    std::vector<OutBlockDesc> d = g->nodes[q][0]->blocks;  // the first member's tables, the node's pair list
+    for (size_t b = 0; b < d.size(); ++b) d[b].pair_base = (int32_t)(b * (size_t)g->fused[q].stride);
+    if (!d.empty()) HIP_TRY(hipMemcpy(ws + g->fused[q].blocks, d.data(), d.size() * sizeof(OutBlockDesc), hipMemcpyHostToDevice));
+  }
+  std::vector<double> one(g->nodes.size(), 1.0), zero(g->nodes.size(), 0.0);
+  group_descs(g, ws, one.data(), zero.data(), g->sdesc, g->pdesc);
+  HIP_TRY(hipMemcpy(ws + g->off_sdesc, g->sdesc.data(), g->sdesc.size() * sizeof(ScreenDesc), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(ws + g->off_pdesc, g->pdesc.data(), g->pdesc.size() * sizeof(ProblemDesc), hipMemcpyHostToDevice));
   std::vector<int32_t> items(g->sitem_prob);
   items.insert(items.end(), g->sitem_block.begin(), g->sitem_block.end());
@@ -1366,8 +1507,11 @@ static int group_enqueue_class(tamm_group* g, int c, hipStream_t s) {
   return TAMM_OK;
 }
 
-// Enqueue the group's kernels (counter reset, screening, persistent contraction).
-static int group_enqueue(tamm_group* g, hipStream_t s) {
+namespace tamm {
+
+// Enqueue the group's kernels (screening, then per class a counter reset and the persistent
+// contraction), consuming the descriptors in the workspace.
+int group_enqueue(tamm_group* g, hipStream_t s) {
   ScreenParams sp{};
   sp.probs = (const ScreenDesc*)(g->ws + g->off_sdesc);
   sp.item_prob = (const int32_t*)(g->ws + g->off_sitems);
@@ -1382,40 +1526,60 @@ static int group_enqueue(tamm_group* g, hipStream_t s) {
   return TAMM_OK;
 }
 
+}  // namespace tamm
+
 static int group_check(tamm_group* g) {
   if (!g->bound) return fail(TAMM_ERR_UNBOUND, "group workspace is not bound (or the configuration changed since binding)");
   for (auto* p : g->plans) {
     int rc = check_tensors(p);
     if (rc != TAMM_OK) return rc;
   }
-  // members must be independent: no member writes storage that another member reads or writes
-  for (size_t i = 0; i < g->plans.size(); ++i)
-    for (size_t j = 0; j < g->plans.size(); ++j) {
+  // nodes must be independent: no node writes storage that another node reads or writes
+  for (size_t i = 0; i < g->nodes.size(); ++i)
+    for (size_t j = 0; j < g->nodes.size(); ++j) {
       if (i == j) continue;
-      const tamm_plan* a = g->plans[i];
-      const tamm_plan* b = g->plans[j];
-      if (overlaps(a->out, b->out) || overlaps(a->out, b->lhs) || overlaps(a->out, b->rhs))
-        return fail(TAMM_ERR_ARG, "group members %zu and %zu are not independent (member %zu writes storage member %zu uses)", i,
-                    j, i, j);
+      const tamm_tensor* out = g->nodes[i][0]->out;
+      for (const tamm_plan* b : g->nodes[j])
+        if (overlaps(out, b->out) || overlaps(out, b->lhs) || overlaps(out, b->rhs))
+          return fail(TAMM_ERR_ARG, "group members %zu and %zu are not independent (member %zu writes storage member %zu uses)",
+                      i, j, i, j);
     }
   return TAMM_OK;
 }
 
-// Refresh the device problem descriptors when storage bindings or coefficients changed.
-static int group_update_desc(tamm_group* g, const double* alpha, const double* beta, hipStream_t s, bool* changed) {
-  *changed = false;
-  for (size_t q = 0; q < g->plans.size(); ++q) {
-    ProblemDesc d = problem_desc(g->plans[q], g->ws, g->lays[q], nullptr, 1, alpha[q], beta[q]);
-    if (memcmp(&d, &g->pdesc[q], sizeof(d)) != 0) {
-      g->pdesc[q] = d;
-      *changed = true;
-    }
-  }
+namespace tamm {
+
+// Refresh the device descriptors when storage bindings or coefficients changed (after draining
+// the stream: earlier launches may still read the old ones).
+int group_update_desc(tamm_group* g, const double* alpha, const double* beta, hipStream_t s, bool* changed) {
+  std::vector<ScreenDesc> sds;
+  std::vector<ProblemDesc> pds;
+  group_descs(g, g->ws, alpha, beta, sds, pds);
+  const bool sc = memcmp(sds.data(), g->sdesc.data(), sds.size() * sizeof(ScreenDesc)) != 0;
+  const bool pc = memcmp(pds.data(), g->pdesc.data(), pds.size() * sizeof(ProblemDesc)) != 0;
+  *changed = sc || pc;
   if (*changed) {
     HIP_TRY(hipStreamSynchronize(s));
-    HIP_TRY(hipMemcpy(g->ws + g->off_pdesc, g->pdesc.data(), g->pdesc.size() * sizeof(ProblemDesc), hipMemcpyHostToDevice));
+    if (sc) HIP_TRY(hipMemcpy(g->ws + g->off_sdesc, sds.data(), sds.size() * sizeof(ScreenDesc), hipMemcpyHostToDevice));
+    if (pc) HIP_TRY(hipMemcpy(g->ws + g->off_pdesc, pds.data(), pds.size() * sizeof(ProblemDesc), hipMemcpyHostToDevice));
+    g->sdesc.swap(sds);
+    g->pdesc.swap(pds);
   }
   return TAMM_OK;
+}
+
+int group_check_bound(tamm_group* g) { return group_check(g); }
+size_t group_node_count(const tamm_group* g) { return g->nodes.size(); }
+
+}  // namespace tamm
+
+// Whether the descriptors in the workspace match the current bindings and these coefficients.
+static bool group_desc_current(const tamm_group* g, const double* alpha, const double* beta) {
+  std::vector<ScreenDesc> sds;
+  std::vector<ProblemDesc> pds;
+  group_descs(g, g->ws, alpha, beta, sds, pds);
+  return memcmp(sds.data(), g->sdesc.data(), sds.size() * sizeof(ScreenDesc)) == 0 &&
+         memcmp(pds.data(), g->pdesc.data(), pds.size() * sizeof(ProblemDesc)) == 0;
 }
 
 extern "C" int tamm_group_execute(tamm_group* g, const double* alpha, const double* beta, void* stream) {
@@ -1425,23 +1589,16 @@ extern "C" int tamm_group_execute(tamm_group* g, const double* alpha, const doub
   hipStream_t s = (hipStream_t)stream;
   bool changed = false;
   if (g->exec) {
-    const size_t n = g->plans.size();
+    const size_t n = g->nodes.size();
     const bool same = std::equal(alpha, alpha + n, g->g_alpha.begin()) && std::equal(beta, beta + n, g->g_beta.begin());
-    if (same) {
-      // the captured graph used the current descriptors; make sure bindings did not move
-      for (size_t q = 0; q < n && !changed; ++q) {
-        ProblemDesc d = problem_desc(g->plans[q], g->ws, g->lays[q], nullptr, 1, alpha[q], beta[q]);
-        changed = memcmp(&d, &g->pdesc[q], sizeof(d)) != 0;
-      }
-      if (!changed) {
-        HIP_TRY(hipGraphLaunch(g->exec, s));
-        return ok();
-      }
+    if (same && group_desc_current(g, alpha, beta)) {  // the captured graph used these descriptors
+      HIP_TRY(hipGraphLaunch(g->exec, s));
+      return ok();
     }
     group_drop_graph(g);
   }
   // eager path: descriptor refresh when something changed (after the stream drained, so that
-  // earlier launches that read the old descriptors are finished), then the three launches
+  // earlier launches that read the old descriptors are finished), then the launches
   rc = group_update_desc(g, alpha, beta, s, &changed);
   if (rc != TAMM_OK) return rc;
   rc = group_enqueue(g, s);
@@ -1481,19 +1638,20 @@ extern "C" int tamm_group_capture(tamm_group* g, const double* alpha, const doub
   }
   g->graph = graph;
   g->exec = exec;
-  g->g_alpha.assign(alpha, alpha + g->plans.size());
-  g->g_beta.assign(beta, beta + g->plans.size());
+  g->g_alpha.assign(alpha, alpha + g->nodes.size());
+  g->g_beta.assign(beta, beta + g->nodes.size());
   return ok();
 }
 
-extern "C" int tamm_group_autotune(tamm_group* g, void* stream, const char* cache_path, int32_t reps) {
-  if (!g) return fail(TAMM_ERR_ARG, "null group");
+namespace tamm {
+
+// Autotuner of a group (see tamm_group_autotune): per gather layout class, the fastest
+// (configuration, grid) of the class's own launch, timed with alpha = 0, beta = 1.
+int group_autotune(tamm_group* g, hipStream_t s, const char* cache_path, int32_t reps) {
   int rc = group_check(g);
   if (rc != TAMM_OK) return rc;
   void* ws = g->ws;
   const size_t bytes = g->ws_bytes;
-  hipStream_t s = (hipStream_t)stream;
-  // per gather layout class, the fastest (configuration, grid) of the class's own launch
   CacheEntry best[kLayouts];
   char tag[kLayouts][16];
   bool cached = true;
@@ -1505,7 +1663,7 @@ extern "C" int tamm_group_autotune(tamm_group* g, void* stream, const char* cach
   if (!cached) {
     if (reps <= 0) reps = 3;
     for (int c = 0; c < kLayouts; ++c) best[c] = CacheEntry{-1, 1, 0, 1e30};
-    std::vector<double> a0(g->plans.size(), 0.0), b1(g->plans.size(), 1.0);
+    std::vector<double> a0(g->nodes.size(), 0.0), b1(g->nodes.size(), 1.0);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -1519,7 +1677,9 @@ extern "C" int tamm_group_autotune(tamm_group* g, void* stream, const char* cach
         if ((rc = group_bind(g, ws, bytes)) != TAMM_OK) break;
         // screening and a warm-up; alpha = 0, beta = 1 leaves every output unchanged (finite
         // operands), and the classes' launches below reuse that screening
-        if ((rc = tamm_group_execute(g, a0.data(), b1.data(), stream)) != TAMM_OK) break;
+        bool changed = false;
+        if ((rc = group_update_desc(g, a0.data(), b1.data(), s, &changed)) != TAMM_OK) break;
+        if ((rc = group_enqueue(g, s)) != TAMM_OK) break;
         for (int c = 0; c < kLayouts && rc == TAMM_OK; ++c) {
           if (g->cls_begin[c + 1] == g->cls_begin[c]) continue;
           HIP_TRY(hipEventRecord(e0, s));
@@ -1547,7 +1707,29 @@ extern "C" int tamm_group_autotune(tamm_group* g, void* stream, const char* cach
   if (rc != TAMM_OK) return rc;
   for (int c = 0; c < kLayouts; ++c) g->grid[c] = best[c].config >= 0 ? best[c].grid : 0;
   if (g->ws_size > bytes) return fail(TAMM_ERR_WORKSPACE, "cached configuration needs %zu bytes", g->ws_size);
-  rc = group_bind(g, ws, bytes);
+  return group_bind(g, ws, bytes);
+}
+
+size_t group_workspace_size(const tamm_group* g) { return g->ws_size; }
+
+// The largest workspace any configuration of the group needs (the autotuner's candidates).
+size_t group_autotune_workspace_size(tamm_group* g) {
+  size_t best = g->ws_size;
+  int cfgs[kLayouts];
+  for (int c = 0; c < kLayouts; ++c) cfgs[c] = g->cfg[c];
+  for (int k = 0; k < f64_config_count(); ++k)
+    if (group_configure(g, k) == TAMM_OK) best = std::max(best, g->ws_size);
+  (void)group_configure_classes(g, cfgs);
+  return best;
+}
+
+int group_bind_ws(tamm_group* g, void* ws, size_t bytes) { return group_bind(g, ws, bytes); }
+
+}  // namespace tamm
+
+extern "C" int tamm_group_autotune(tamm_group* g, void* stream, const char* cache_path, int32_t reps) {
+  if (!g) return fail(TAMM_ERR_ARG, "null group");
+  const int rc = group_autotune(g, (hipStream_t)stream, cache_path, reps);
   return rc == TAMM_OK ? ok() : rc;
 }
 
@@ -1568,3 +1750,19 @@ extern "C" int tamm_group_destroy(tamm_group* g) {
   delete g;
   return ok();
 }
+
+namespace tamm {
+
+void plan_io(const tamm_plan* p, tamm_tensor** out, const tamm_tensor** lhs, const tamm_tensor** rhs, int* precision) {
+  *out = p->out;
+  *lhs = p->lhs;
+  *rhs = p->rhs;
+  *precision = p->prec;
+}
+
+bool plans_fusable(tamm_plan* a, tamm_plan* b) {
+  const std::vector<tamm_plan*> node{a, b};
+  return a->prec == TAMM_PREC_F64 && b->prec == TAMM_PREC_F64 && check_fusable(node) == TAMM_OK;
+}
+
+}  // namespace tamm
