@@ -18,7 +18,9 @@ What it follows (arXiv 2201.01257, "TAMM: Tensor Algebra for Many-body Methods")
   form (Eq. tamm_cc11), spin-explicit sub-spaces (Eq. tamm_cc-Spin), Sec. IV-A-1;
 * the SetOp and AddOp (with a label permutation) of the same grammar (Fig. 3, rules 5-7);
 * the orbital-energy-denominator update that turns a doubles residual into new amplitudes
-  (the Jacobi step of CD-CCSD, named in Sec. IV-B-1).
+  (the Jacobi step of CD-CCSD, named in Sec. IV-B-1);
+* the ladder over integrals rebuilt from Cholesky vectors, Eq. (cc12), with the rebuilt tensor
+  as a lambda tensor whose blocks are computed on demand (Sec. III-A).
 
 Readings taken where the paper is silent are listed in the module docstrings they affect.
 
@@ -34,6 +36,7 @@ from .tiling import Space, spin_conserving
 from .blocksparse import BlockTensor, LazyBlocks, contract, screen, denominator_update, parse_labels
 from .adjoint import contract_vjp
 from .elementwise import add, set_value
+from .cholesky import cholesky_ladder, v_from_cholesky, spin_diagonal
 
 __all__ = [
     "Space",
@@ -47,4 +50,7 @@ __all__ = [
     "contract_vjp",
     "add",
     "set_value",
+    "cholesky_ladder",
+    "v_from_cholesky",
+    "spin_diagonal",
 ]

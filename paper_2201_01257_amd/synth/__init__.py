@@ -16,7 +16,12 @@ Sec. IV-A-1, which are not available here):
   pattern, scaled back to unit variance, zero where spin is not conserved;
 * doubles amplitudes ``T2[c,d,i,j] = w / (e_i + e_j - e_c - e_d)``, singles
   ``T1[a,i] = w / (e_i - e_a)``, with w ~ N(0, 0.1^2) and zero where spin is not conserved;
-* generic tensors ``N_<name>`` are plain N(0, 0.1^2), optionally zeroed by the spin rule.
+* generic tensors ``N_<name>`` are plain N(0, 0.1^2), optionally zeroed by the spin rule;
+* Cholesky vectors ``B_vvx`` of the two-electron integrals, B[p,q,L] = (pq|L) over two virtual
+  spin-orbitals and an auxiliary index L (pattern letter ``x``, ``n_aux`` values): zero unless p
+  and q have the same spin, else one N(0, s^2) value per unordered pair of spatial orbitals and
+  L (symmetric in p, q; the alpha and beta copies equal), with s^2 = 0.1 / sqrt(2 n_aux), so
+  that the integrals rebuilt from them have about the spread of ``V_vvvv``.
 """
 
 from __future__ import annotations
@@ -38,7 +43,7 @@ SIGMA = 0.1
 E_OCC = (-2.0, -0.5)
 E_VIR = (0.2, 3.0)
 
-KIND_NORMAL, KIND_SYMMETRIC, KIND_AMPLITUDE = 0, 1, 2
+KIND_NORMAL, KIND_SYMMETRIC, KIND_AMPLITUDE, KIND_CHOLESKY = 0, 1, 2, 3
 
 
 def build_library(force: bool = False) -> str:
@@ -101,18 +106,19 @@ class Orbitals:
     """Occupied/virtual spin-orbital spaces (alpha half first) and their orbital energies."""
 
     def __init__(self, n_occ: int, n_vir: int, seed: int = SEED, n_occ_alpha: Optional[int] = None,
-                 n_vir_alpha: Optional[int] = None):
+                 n_vir_alpha: Optional[int] = None, n_aux: int = 0):
         self.n_occ, self.n_vir, self.seed = int(n_occ), int(n_vir), int(seed)
+        self.n_aux = int(n_aux)  # auxiliary (Cholesky) index extent, pattern letter "x"
         self.n_occ_alpha = self.n_occ // 2 if n_occ_alpha is None else int(n_occ_alpha)
         self.n_vir_alpha = self.n_vir // 2 if n_vir_alpha is None else int(n_vir_alpha)
         self.e_occ = uniform(self.seed, "e_occ", self.n_occ, *E_OCC)
         self.e_vir = uniform(self.seed, "e_vir", self.n_vir, *E_VIR)
 
     def extent(self, c: str) -> int:
-        return self.n_occ if c == "o" else self.n_vir
+        return {"o": self.n_occ, "v": self.n_vir, "x": self.n_aux}[c]
 
     def n_alpha(self, c: str) -> int:
-        return self.n_occ_alpha if c == "o" else self.n_vir_alpha
+        return {"o": self.n_occ_alpha, "v": self.n_vir_alpha, "x": self.n_aux}[c]
 
     def energy(self, c: str) -> np.ndarray:
         return self.e_occ if c == "o" else self.e_vir
@@ -138,7 +144,13 @@ class Orbitals:
         esign = None
         vclass = np.ascontiguousarray(np.array([1 if c == "v" else 0 for c in pattern], dtype=np.int8))
         keep: list = []
-        if name.startswith("V_"):
+        sigma = SIGMA
+        if name == "B_vvx":
+            kind = KIND_CHOLESKY
+            if pattern != "vvx" or self.n_aux <= 0:
+                raise ValueError("B_vvx has pattern vvx and needs n_aux > 0")
+            sigma = cholesky_sigma(self.n_aux)
+        elif name.startswith("V_"):
             kind = KIND_SYMMETRIC
             if name[2:] != pattern or rank != 4:
                 raise ValueError("V_<pattern> tensors are rank 4 and named after their pattern")
@@ -158,7 +170,7 @@ class Orbitals:
         if out.size == 0:
             return out
         rc = _load().synth_fill(self.seed, tag(name), kind, rank, dims.ctypes.data, nalpha.ctypes.data,
-                                lo_a.ctypes.data, ext_a.ctypes.data, SIGMA,
+                                lo_a.ctypes.data, ext_a.ctypes.data, sigma,
                                 ctypes.cast(energy_ptrs, ctypes.c_void_p) if energy_ptrs is not None else None,
                                 esign.ctypes.data if esign is not None else None, vclass.ctypes.data,
                                 1, out.ctypes.data)
@@ -168,6 +180,11 @@ class Orbitals:
 
     def dense(self, name: str, pattern: str) -> np.ndarray:
         return self.fill(name, pattern, [0] * len(pattern), [self.extent(c) for c in pattern])
+
+
+def cholesky_sigma(n_aux: int) -> float:
+    """Spread of the synthetic Cholesky vectors for ``n_aux`` auxiliary values (see the recipe)."""
+    return float(np.sqrt(SIGMA / np.sqrt(2.0 * n_aux)))
 
 
 # The CCSD doubles-residual term set used as the workload (contraction shapes, spin-orbital
@@ -214,6 +231,16 @@ WORKLOADS = {
 DENSE4D = {
     "dense4d_n200_t40": dict(n=200, tile=40, proxy_n=80),
     "dense4d_n160_t40": dict(n=160, tile=40, proxy_n=80),
+}
+
+
+# The particle-particle ladder with V_vvvv rebuilt from Cholesky vectors, Eq. (cc12):
+# V[a,b,c,d] = sum_L B[a,c,L] B[b,d,L] - B[a,d,L] B[b,c,L].  n_aux = 6.29 x the spatial orbitals
+# (O + V) / 2, the ratio of the paper's aug-cc-pVDZ example (7810 vectors for 146 + 1096
+# orbitals, Sec. V); the auxiliary index is one tile.
+CHOLESKY = {
+    "chol_ladder_o40_v200_t40": dict(n_occ=40, n_vir=200, tile_occ=40, tile_vir=40, n_aux=755, tile_aux=755),
+    "chol_ladder_o64_v320_t64": dict(n_occ=64, n_vir=320, tile_occ=64, tile_vir=64, n_aux=1207, tile_aux=1207),
 }
 
 

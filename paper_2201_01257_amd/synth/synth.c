@@ -49,7 +49,7 @@ int synth_uniform(uint64_t seed, uint64_t tag, int64_t first, int64_t n, double 
   return 0;
 }
 
-enum { SYNTH_NORMAL = 0, SYNTH_SYMMETRIC = 1, SYNTH_AMPLITUDE = 2 };
+enum { SYNTH_NORMAL = 0, SYNTH_SYMMETRIC = 1, SYNTH_AMPLITUDE = 2, SYNTH_CHOLESKY = 3 };
 
 /* Fill a dense row-major box out[ext[0]]...[ext[rank-1]] whose corner is lo[] in a tensor of
  * dense shape dims[].  nalpha[d]: indices below it have spin alpha (0), the rest beta (1).
@@ -61,6 +61,12 @@ enum { SYNTH_NORMAL = 0, SYNTH_SYMMETRIC = 1, SYNTH_AMPLITUDE = 2 };
  * kind SYNTH_AMPLITUDE: sigma * z(idx) / D(p) with D = sum of energy[d][p_d] over dims with
  *                       esign[d] > 0 in dimension order, then minus energy[d][p_d] over dims
  *                       with esign[d] < 0 in dimension order.
+ * kind SYNTH_CHOLESKY:  rank 3 (p, q, L), p and q in one spin-orbital space of dims[0] ==
+ *                       dims[1] with nalpha[0] == nalpha[1], L auxiliary.  Zero unless p and q
+ *                       have the same spin; otherwise sigma * z(idx) at the index of the
+ *                       unordered pair of their spatial orbitals (p - nalpha for beta) and L, so
+ *                       the value is symmetric in (p, q) and equal for the alpha and beta
+ *                       copies of a spatial pair (vectors of spatial-orbital integrals).
  * spin_zero != 0 sets elements that break spin conservation (first half of the dims against
  * the second half, even ranks) to exactly zero.
  */
@@ -70,6 +76,7 @@ int synth_fill(uint64_t seed, uint64_t tag, int kind, int rank, const int64_t* d
   if (rank < 1 || rank > SYNTH_MAX_RANK || !dims || !lo || !ext || !out) return -1;
   if (kind == SYNTH_SYMMETRIC && (rank != 4 || !vclass)) return -1;
   if (kind == SYNTH_AMPLITUDE && (!energy || !esign)) return -1;
+  if (kind == SYNTH_CHOLESKY && (rank != 3 || !nalpha || dims[0] != dims[1] || nalpha[0] != nalpha[1])) return -1;
   if (spin_zero && !nalpha) return -1;
   for (int d = 0; d < rank; ++d)
     if (lo[d] < 0 || ext[d] < 0 || lo[d] + ext[d] > dims[d]) return -1;
@@ -112,7 +119,18 @@ int synth_fill(uint64_t seed, uint64_t tag, int kind, int rank, const int64_t* d
         }
       }
       double v;
-      if (kind == SYNTH_SYMMETRIC) {
+      if (kind == SYNTH_CHOLESKY) {
+        const int64_t na = nalpha[0], nsp = na > dims[0] - na ? na : dims[0] - na;
+        const int b0 = p[0] >= na, b1 = p[1] >= na;
+        if (b0 != b1) {
+          o[c] = 0.0;
+          continue;
+        }
+        const int64_t s0 = p[0] - (b0 ? na : 0), s1 = p[1] - (b1 ? na : 0);
+        const int64_t lo_s = s0 < s1 ? s0 : s1, hi_s = s0 < s1 ? s1 : s0;
+        const uint64_t lin = ((uint64_t)lo_s * (uint64_t)nsp + (uint64_t)hi_s) * (uint64_t)dims[2] + (uint64_t)p[2];
+        v = sigma * normal_at(key, lin);
+      } else if (kind == SYNTH_SYMMETRIC) {
         /* orbit members summed in ascending linear index, so every member of an orbit gets the
          * bitwise-identical value */
         uint64_t lins[4];
