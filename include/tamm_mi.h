@@ -443,6 +443,58 @@ int tamm_sched_op_info(const tamm_sched* s, int32_t op, int32_t* level, int32_t*
 int tamm_sched_destroy(tamm_sched* s);
 
 /* ------------------------------------------------------------------------------------------
+ * Row views (the view tensors of Sec. III-A: a tensor of another shape over existing storage,
+ * no allocation).  *out receives a new tensor handle whose first dimension holds tiles
+ * [tile_lo, tile_hi) of parent's first dimension (the other dimensions, the block rule and the
+ * order of the blocks are parent's), and *elem_offset the element offset in parent's storage at
+ * which the view's storage starts: parent's blocks whose first tile lies in the range are
+ * contiguous there (lexicographic block order).  Bind the view to parent's storage plus
+ * 8 * *elem_offset bytes.  Host only; the view does not track later rebinding of parent.
+ * ERR_ARG on an empty or out-of-range tile range.  Destroy with tamm_tensor_destroy.
+ * ------------------------------------------------------------------------------------------ */
+int tamm_tensor_view_rows(const tamm_tensor* parent, int32_t tile_lo, int32_t tile_hi, tamm_tensor** out,
+                          int64_t* elem_offset);
+
+/* ------------------------------------------------------------------------------------------
+ * Particle-particle ladder over integrals rebuilt from Cholesky vectors (Sec. IV-A-1, Eq. (cc12);
+ * the integral tensor as a lambda tensor of Sec. III-A, computed where it is used):
+ *
+ *   R[a,b,i,j] = beta * R[a,b,i,j] + alpha * sum_cd V[a,b,c,d] T[c,d,i,j],
+ *   V[a,b,c,d] = sum_L B[a,c,L] B[b,d,L] - B[a,d,L] B[b,c,L].
+ *
+ * R and T: rank 4 (vir, vir, occ, occ), one virtual space for both leading dimensions of R, T
+ * and B, R and T sharing the occupied spaces.  B: rank 3 (vir, vir, aux), the vectors (pq|L),
+ * stored with whatever non-zero check it was created with (spin-diagonal for molecular
+ * integrals); unstored blocks read as zero.  V is never formed: the operation runs as
+ *   Tm[c,d,i,j] = T[c,d,i,j] - T[d,c,i,j]                          (two AddOps, HBM-bound)
+ * and, for each strip of `strip_tiles` tiles of a (0 = one tile per strip),
+ *   G[a,c,b,d]  = sum_L B[a,c,L] B[b,d,L]                          (float64 matrix cores)
+ *   R[a,b,i,j]  = beta R + alpha sum_cd G[a,c,b,d] Tm[c,d,i,j]     (float64 matrix cores)
+ * which equals the definition (rename c <-> d in the second term).  G is stored only on the
+ * blocks where some auxiliary tile pairs two stored B blocks.
+ * Workspace (caller-owned, 256-byte aligned): Tm, one strip of G, and the tables of the strips'
+ * plans (sized for any configuration the autotuner may pick); binding copies tables in
+ * (synchronous).  R, T and B must outlive the handle and keep their storage disjoint from each
+ * other and from the workspace; the handle reads their current bindings at every call.
+ * Execute enqueues everything on stream.  Autotune runs the plan autotuner on every strip's two
+ * plans (R unchanged for finite values; synchronises the stream).  Stats: useful flops of the pair
+ * products and of the strip ladders, strips, largest G strip and Tm in elements (any pointer may
+ * be NULL).  strip_plans exposes a strip's two plans (owned by the handle) for inspection.
+ * ERR_SHAPE / ERR_LABEL when the tensors do not fit the pattern above.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct tamm_chol tamm_chol;
+int tamm_chol_ladder_create(tamm_tensor* r, const tamm_tensor* t, const tamm_tensor* b, int32_t strip_tiles,
+                            tamm_chol** out);
+int tamm_chol_ladder_workspace_size(const tamm_chol* c, size_t* bytes);
+int tamm_chol_ladder_bind_workspace(tamm_chol* c, void* workspace, size_t bytes);
+int tamm_chol_ladder_execute(tamm_chol* c, double alpha, double beta, void* stream);
+int tamm_chol_ladder_autotune(tamm_chol* c, void* stream, const char* cache_path, int32_t reps);
+int tamm_chol_ladder_stats(const tamm_chol* c, double* build_flops, double* ladder_flops, int64_t* strips,
+                           int64_t* g_max_elements, int64_t* tm_elements);
+int tamm_chol_ladder_strip_plans(const tamm_chol* c, int32_t strip, tamm_plan** build, tamm_plan** ladder);
+int tamm_chol_ladder_destroy(tamm_chol* c);
+
+/* ------------------------------------------------------------------------------------------
  * Diagnostic: execute one matrix-core instruction on one wave with caller data (device
  * pointers, enqueued on stream), for tests of its lane layout and of the rounding of its float32
  * accumulation on inputs whose exact results are known.  The contraction path never calls it.

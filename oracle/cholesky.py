@@ -56,9 +56,9 @@ def v_from_cholesky(b: BlockTensor) -> BlockTensor:
         acc = np.zeros(out.block_shape(tile))
         for tl in range(aux.ntiles):
             if b.is_stored((ta, tc, tl)) and b.is_stored((tb, td, tl)):
-                acc += np.einsum("acL,bdL->abcd", b.blocks[(ta, tc, tl)], b.blocks[(tb, td, tl)])
+                acc += np.einsum("acL,bdL->abcd", b.blocks[(ta, tc, tl)], b.blocks[(tb, td, tl)], optimize=True)
             if b.is_stored((ta, td, tl)) and b.is_stored((tb, tc, tl)):
-                acc -= np.einsum("adL,bcL->abcd", b.blocks[(ta, td, tl)], b.blocks[(tb, tc, tl)])
+                acc -= np.einsum("adL,bcL->abcd", b.blocks[(ta, td, tl)], b.blocks[(tb, tc, tl)], optimize=True)
         return acc
 
     out.blocks = LazyBlocks(block)

@@ -102,6 +102,15 @@ SIGNATURES = {
     "tamm_sched_info": (c_int, [c_vp, P(c_i32), P(c_i32), P(c_i32)]),
     "tamm_sched_op_info": (c_int, [c_vp, c_i32, P(c_i32), P(c_i32)]),
     "tamm_sched_destroy": (c_int, [c_vp]),
+    "tamm_tensor_view_rows": (c_int, [c_vp, c_i32, c_i32, P(c_vp), P(c_i64)]),
+    "tamm_chol_ladder_create": (c_int, [c_vp, c_vp, c_vp, c_i32, P(c_vp)]),
+    "tamm_chol_ladder_workspace_size": (c_int, [c_vp, P(c_size_t)]),
+    "tamm_chol_ladder_bind_workspace": (c_int, [c_vp, c_vp, c_size_t]),
+    "tamm_chol_ladder_execute": (c_int, [c_vp, c_dbl, c_dbl, c_vp]),
+    "tamm_chol_ladder_autotune": (c_int, [c_vp, c_vp, c_char_p, c_i32]),
+    "tamm_chol_ladder_stats": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_i64), P(c_i64), P(c_i64)]),
+    "tamm_chol_ladder_strip_plans": (c_int, [c_vp, c_i32, P(c_vp), P(c_vp)]),
+    "tamm_chol_ladder_destroy": (c_int, [c_vp]),
 }
 
 STATUS = {

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtamm_mi.so")
-SOURCES = ["capi_core.cpp", "plan.cpp", "denominator.cpp", "addop.cpp", "sched.cpp", "kernels.hip", "kernels_mixed.hip",
+SOURCES = ["capi_core.cpp", "plan.cpp", "denominator.cpp", "addop.cpp", "sched.cpp", "cholesky.cpp", "kernels.hip", "kernels_mixed.hip",
            "kernels_elem.hip", "diag.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

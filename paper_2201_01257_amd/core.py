@@ -228,9 +228,59 @@ class Tensor:
             d[tuple(slice(l, l + e) for l, e in zip(lo, ext))] = flat[off:off + int(np.prod(ext))].reshape(ext)
         return d
 
+    def view_rows(self, tile_lo: int, tile_hi: int) -> "Tensor":
+        """A tensor over tiles [tile_lo, tile_hi) of the first dimension sharing this tensor's
+        storage (tamm_tensor_view_rows); bound to the matching slice of ``data``."""
+        lib = load()
+        h = ctypes.c_void_p()
+        base = ctypes.c_int64()
+        check(lib.tamm_tensor_view_rows(self._h, int(tile_lo), int(tile_hi), ctypes.byref(h), ctypes.byref(base)))
+        v = Tensor.__new__(Tensor)
+        v._h = h
+        v.parent = self  # keeps the storage alive
+        first = self.spaces[0]
+        sl = slice(int(tile_lo), int(tile_hi))
+        # the first space is a slice of this tensor's (no library handle of its own): its tiles,
+        # with offsets counted from the slice's start
+        v.spaces = [_SpaceSlice(first.sizes[sl], first.spins[sl])] + list(self.spaces[1:])
+        v.rank = self.rank
+        v.nonzero = self.nonzero
+        n = ctypes.c_int64()
+        check(lib.tamm_tensor_numel(h, ctypes.byref(n)))
+        v.numel = n.value
+        nb = ctypes.c_int64()
+        check(lib.tamm_tensor_blocks(h, ctypes.byref(nb), None, None))
+        v.nblocks = nb.value
+        v.block_tiles = np.zeros((v.nblocks, v.rank), dtype=np.int32)
+        v.block_off = np.zeros(v.nblocks, dtype=np.int64)
+        if v.nblocks:
+            check(lib.tamm_tensor_blocks(h, ctypes.byref(nb), v.block_tiles.ctypes.data, v.block_off.ctypes.data))
+        v._contract_ws = {}
+        v.view_base = base.value
+        v.data = None
+        if self.data is not None:
+            v.bind(self.data[base.value:base.value + max(v.numel, 1)])
+        return v
+
     def __del__(self, _d=_destroy):
         self._contract_ws = {}
         _d(self, "tamm_tensor_destroy")
+
+
+class _SpaceSlice:
+    """Tile geometry of a run of tiles of a Space (the first dimension of a row view)."""
+
+    def __init__(self, sizes, spins):
+        self.sizes = np.asarray(sizes, dtype=np.int64).copy()
+        self.spins = np.asarray(spins, dtype=np.int8).copy()
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)[:-1]]).astype(np.int64)
+        self.ntiles = len(self.sizes)
+        self.extent = int(self.sizes.sum())
+
+
+def spin_diagonal(tiles, spins) -> bool:
+    """Non-zero check of Cholesky vectors B[p,q,L]: p and q of one spin."""
+    return spins[0] == spins[1]
 
 
 class Plan:
@@ -390,6 +440,55 @@ class Denominator:
 
     def __del__(self, _d=_destroy):
         _d(self, "tamm_denominator_destroy")
+
+
+class CholeskyLadder:
+    """R[abij] = beta R + alpha sum_cd V[abcd] T[cdij] with V rebuilt from Cholesky vectors
+    B[p,q,L] by Eq. (cc12), V never formed (tamm_chol_ladder_*)."""
+
+    def __init__(self, R: Tensor, T: Tensor, B: Tensor, strip_tiles: int = 0):
+        self.R, self.T, self.B = R, T, B
+        lib = load()
+        h = ctypes.c_void_p()
+        check(lib.tamm_chol_ladder_create(R._h, T._h, B._h, int(strip_tiles), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_size_t()
+        check(lib.tamm_chol_ladder_workspace_size(self._h, ctypes.byref(n)))
+        self.ws_bytes = n.value
+        self._ws = None
+        if R.data is not None:  # structure-only tensors (no device) plan without binding
+            self._ws, ptr = _aligned_workspace(self.ws_bytes, R.data.device)
+            check(lib.tamm_chol_ladder_bind_workspace(self._h, ctypes.c_void_p(ptr), self.ws_bytes))
+
+    def execute(self, alpha: float = 0.5, beta: float = 0.0, stream=None):
+        s = current_stream_handle() if stream is None else stream
+        check(load().tamm_chol_ladder_execute(self._h, float(alpha), float(beta), s))
+
+    def autotune(self, cache_path: str = "", reps: int = 3, stream=None):
+        s = current_stream_handle() if stream is None else stream
+        check(load().tamm_chol_ladder_autotune(self._h, s, cache_path.encode(), int(reps)))
+
+    def stats(self) -> dict:
+        bf, lf = ctypes.c_double(), ctypes.c_double()
+        ns, gm, tm_ = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(load().tamm_chol_ladder_stats(self._h, ctypes.byref(bf), ctypes.byref(lf), ctypes.byref(ns),
+                                            ctypes.byref(gm), ctypes.byref(tm_)))
+        return {"build_flops": bf.value, "ladder_flops": lf.value, "strips": ns.value, "g_max_elements": gm.value,
+                "tm_elements": tm_.value, "workspace_bytes": self.ws_bytes}
+
+    def strip_plan_stats(self, strip: int) -> Tuple[dict, dict]:
+        """Plan statistics of one strip's pair product and ladder (tamm_plan_stats)."""
+        b, l = ctypes.c_void_p(), ctypes.c_void_p()
+        check(load().tamm_chol_ladder_strip_plans(self._h, int(strip), ctypes.byref(b), ctypes.byref(l)))
+        res = []
+        for h in (b, l):
+            st = PlanStats()
+            check(load().tamm_plan_stats_get(h, ctypes.byref(st)))
+            res.append({f: getattr(st, f) for f, _ in PlanStats._fields_})
+        return res[0], res[1]
+
+    def __del__(self, _d=_destroy):
+        _d(self, "tamm_chol_ladder_destroy")
 
 
 def set_value(out: Tensor, alpha: float, stream=None) -> Tensor:
@@ -574,4 +673,5 @@ class Group:
         _d(self, "tamm_group_destroy")
 
 
-__all__ = ["Space", "Tensor", "Plan", "Group", "contract", "Denominator", "Add", "set_value", "Scheduler", "TammError", "PRECISIONS"]
+__all__ = ["Space", "Tensor", "Plan", "Group", "contract", "Denominator", "Add", "set_value", "Scheduler", "TammError",
+           "PRECISIONS", "CholeskyLadder", "spin_diagonal"]
