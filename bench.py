@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--tune-cache", default="", help="autotuner cache file")
     ap.add_argument("--no-tune", action="store_true", help="keep the plans' default kernel configurations")
     ap.add_argument("--strip-tiles", type=int, default=1, help="Cholesky ladder: a-tiles per strip of G")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload: skip the config-0, reduced-precision and batched legs")
     ap.add_argument("--ladder-k-splits", type=int, default=0,
                     help="after tuning, run the ladder with this many K splits (0: the tuned choice); for "
                          "counter runs of a second decomposition")
@@ -301,6 +303,17 @@ def main():
         "rel_err": rel,
         "rel_err_tolerance": 1e-12,
     }
+    if not args.no_extras:
+        # the metric's other halves, each with its own parity check and oracle baseline: the smallest
+        # workload (latency), the reduced-precision paths at O=64, V=320, the batched group
+        for name, leg in (("config0_latency", lambda: config0_leg(args)),
+                          ("mixed_o64_v320_t64", lambda: mixed_leg(args, "mixed_o64_v320_t64", ["f64", "bf16x4_aligned"])),
+                          ("batched_256", lambda: batched_leg(args, 5, 2))):
+            t0 = time.time()
+            line[name] = leg()
+            gc.collect()
+            torch.cuda.empty_cache()
+            log(f"[bench] {name} leg done in {time.time() - t0:.1f}s")
     s = json.dumps(line)
     print(s, flush=True)
     if args.json_out:
@@ -515,16 +528,39 @@ def _time(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+# stated relative-error budgets of the precisions and their product ceilings on the matrix cores:
+# float64 and float32 at their own peaks, the split-bfloat16 schemes at the bfloat16 peak divided by
+# the products they do per float64 product (6 and 10)
+MIXED_TOL = {"f64": 1e-12, "f32": 1e-6, "bf16x3": 3e-7, "bf16x4_aligned": 1e-8}
+MIXED_CEILING = {"f64": 78.6, "f32": 157.3, "bf16x3": round(2500.0 / 6, 1), "bf16x4_aligned": 250.0}
+
+
+def _mixed_bounds():
+    """The element-wise bounds of the reduced precisions (kept with the tests that pin them)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import mixed_bound
+
+    return mixed_bound
+
+
 def run_mixed(args):
+    """Ladder + ring at O=64, V=320, tiles of 64, per precision (own JSON line)."""
+    precisions = [args.precision] if args.precision else ["f64", "f32", "bf16x3", "bf16x4_aligned"]
+    res = mixed_leg(args, args.workload, precisions)
+    _emit(args, dict({"metric": METRIC, "workload": args.workload, "unit": "TFLOP/s", "data": "synthetic"}, **res))
+
+
+def mixed_leg(args, workload, precisions):
     """Ladder + ring at O=64, V=320, tiles of 64, per precision; float64 final accumulation and
-    denominator update; error of each term against the float64 oracle on sampled blocks."""
+    denominator update; error of each term against the float64 oracle on sampled blocks, whose
+    oracle time is the CPU baseline."""
     import torch
 
     import oracle
     from paper_2201_01257_amd import core as tm
     from paper_2201_01257_amd import synth
 
-    wl = synth.WORKLOADS[args.workload]
+    wl = synth.WORKLOADS[workload]
     orb = synth.Orbitals(wl["n_occ"], wl["n_vir"])
     g = {c: _gpu_space(tm, orb, c, wl["tile_occ"] if c == "o" else wl["tile_vir"]) for c in "ov"}
     osp = {c: _oracle_space(oracle, orb, c, wl["tile_occ"] if c == "o" else wl["tile_vir"]) for c in "ov"}
@@ -539,33 +575,52 @@ def run_mixed(args):
     e_o = torch.from_numpy(orb.e_occ).cuda()
     e_v = torch.from_numpy(orb.e_vir).cuda()
     denom = tm.Denominator(Tn, R, [e_v, e_v, e_o, e_o], [-1, -1, 1, 1])
-    precisions = [args.precision] if args.precision else ["f64", "f32", "bf16x3", "bf16x4_aligned"]
     terms = {"ladder": (T["V_vvvv"], "abcd", T["T2"], "cdij", 0.5), "ring": (T["V_ovvo"], "mbej", T["T2"], "aeim", 1.0)}
-    # oracle reference on sampled output blocks of each term (computed once)
+    # oracle reference on output blocks sampled from every stored block of R (computed once)
     rng = np.random.default_rng(2201)
     Ro = oracle.BlockTensor([osp[c] for c in "vvoo"])
     tiles = Ro.stored_tiles()
-    small = [t for t in tiles if all(osp["v"].sizes[t[d]] < wl["tile_vir"] for d in (0, 1))]
-    pick = [small[i] for i in rng.choice(len(small), size=2, replace=False)]
-    ref = {}
-    t0 = time.perf_counter()
+    pick = [tiles[i] for i in rng.choice(len(tiles), size=2, replace=False)]
+    ref, ops = {}, {}
+    cpu_s, cpu_flops = 0.0, 0.0
     for term, (L, ll, Rr, rl, a) in terms.items():
         lname = "V_vvvv" if term == "ladder" else "V_ovvo"
         lo = _oracle_tensor(oracle, synth, orb, osp, lname, "vvvv" if term == "ladder" else "ovvo")
         to = _oracle_tensor(oracle, synth, orb, osp, "T2", "vvoo")
+        ops[term] = (lo, to)
+        scr = oracle.screen(Ro, "abij", lo, ll, to, rl)
+        for t in pick:
+            _touch(Ro, "abij", lo, ll, to, rl, t, scr["pairs"][t])  # inputs generated outside the timing
+            cpu_flops += sum(2.0 * float(np.prod(Ro.block_shape(t))) * _kext(lo, ll, "abij", kt, rl, to)
+                             for kt in scr["pairs"][t])
+        t0 = time.perf_counter()
         ref[term] = oracle.contract(Ro, "abij", lo, ll, to, rl, a, 0.0, out_tiles=pick).blocks
-    log(f"[bench] oracle reference on {len(pick)} blocks per term: {time.perf_counter() - t0:.1f}s")
+        cpu_s += time.perf_counter() - t0
+    log(f"[bench] oracle reference on {len(pick)} blocks per term: {cpu_s:.1f}s")
+    bounds = _mixed_bounds()
     results = {}
+    breaches = []
     for prec in precisions:
         plans = {t: tm.Plan(R, "abij", L, ll, Rr, rl, precision=prec) for t, (L, ll, Rr, rl, a) in terms.items()}
         if not args.no_tune:
             for t, p in plans.items():  # the library's autotuner, outside the timed region
                 p.autotune(args.tune_cache, reps=2)
-        errs = {}
+        errs, ratio = {}, {}
         for t, p in plans.items():
             p.execute(terms[t][4], 0.0)
             torch.cuda.synchronize()
-            errs[t] = _rel(R.to_blocks(), ref[t], pick)
+            got = R.to_blocks()
+            errs[t] = _rel(got, ref[t], pick)
+            elem = max(float(np.max(np.abs(got[k] - ref[t][k]))) / float(np.max(np.abs(ref[t][k]))) for k in pick)
+            errs[t] = (max(errs[t][0], elem), errs[t][1])
+            if prec == "f64":
+                ratio[t] = errs[t][0] / 1e-12
+            else:
+                lo, to = ops[t]
+                bd = bounds.bound_blocks(prec, Ro, "abij", lo, terms[t][1], to, terms[t][3], terms[t][4], pick)
+                ratio[t] = bounds.check(got, ref[t], bd, pick)
+            if ratio[t] > 1.0 or errs[t][0] > MIXED_TOL[prec]:
+                breaches.append((prec, t, errs[t][0], ratio[t]))
         ms = {}
         for t, p in plans.items():
             ms[t] = _time(torch, lambda p=p, a=terms[t][4]: p.execute(a, 0.0), max(2, args.steps // 2), 1)
@@ -577,23 +632,101 @@ def run_mixed(args):
 
         step_ms = _time(torch, step, max(2, args.steps // 2), 1)
         fl = {t: p.stats()["useful_flops"] for t, p in plans.items()}
+        ceiling = MIXED_CEILING[prec]
         results[prec] = {
             "step_ms": round(step_ms, 3),
             "step_tflops": round(sum(fl.values()) / step_ms / 1e9, 3),
-            "terms": {t: {"ms": round(ms[t], 3), "tflops": round(fl[t] / ms[t] / 1e9, 3), "rel_err": float(f"{errs[t][0]:.3e}"),
-                          "max_abs_err": float(f"{errs[t][1]:.3e}"), "config": p.config_name()} for t, p in plans.items()},
+            "product_ceiling_tflops": ceiling,
+            "terms": {t: {"ms": round(ms[t], 3), "tflops": round(fl[t] / ms[t] / 1e9, 3),
+                          "frac": round(fl[t] / ms[t] / 1e9 / ceiling, 4),
+                          "rel_err": float(f"{errs[t][0]:.3e}"), "max_abs_err": float(f"{errs[t][1]:.3e}"),
+                          "rel_err_tolerance": MIXED_TOL[prec], "bound_ratio": float(f"{ratio[t]:.3e}"),
+                          "config": p.config_name()} for t, p in plans.items()},
         }
         log(f"[bench] {prec}: {results[prec]}")
         del plans
         torch.cuda.empty_cache()
-    _emit(args, {"metric": METRIC, "workload": args.workload, "unit": "TFLOP/s", "data": "synthetic",
-                 "sampled_blocks": [list(map(int, t)) for t in pick], "results": results,
-                 "peaks_tflops": {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}})
+    if breaches:
+        raise SystemExit(f"mixed-precision error above its bound or tolerance: {breaches}")
+    cpu = {"value": round(cpu_flops / cpu_s / 1e12, 5), "unit": "TFLOP/s", "cores": int(_blas_threads()),
+           "kind": "oracle",
+           "sample": f"{len(pick)} seeded output blocks of R for each of ladder and ring (float64 oracle, "
+                     f"{cpu_flops / 1e9:.1f} GFLOP useful, {cpu_s:.1f} s; input generation not timed)",
+           "seconds": round(cpu_s, 2)}
+    return {"workload": workload, "sampled_blocks": [list(map(int, t)) for t in pick], "results": results,
+            "cpu_baseline": cpu,
+            "peaks_tflops": {"f64": 78.6, "f32": 157.3, "bf16": 2500.0},
+                 "error_checks": "per term: max(relative Frobenius, max |err| / max |ref|) <= rel_err_tolerance, and "
+                                 "every sampled element within the worst-case bound of the precision "
+                                 "(bound_ratio = largest |err| / bound <= 1)"}
+
+
+def config0_leg(args, reps=200):
+    """The smallest workload: the ladder at O=10, V=40 spin-orbitals in tiles of 5 (2560 tile pairs
+    of 25x25x25 after screening, 80 MFLOP useful), float64.  Latency-bound: wall time per execution
+    (screening + contraction) issued eagerly and replayed from a captured hipGraph (one-plan group);
+    parity of every block and the oracle's time on the whole problem."""
+    import torch
+
+    import oracle
+    from paper_2201_01257_amd import core as tm
+    from paper_2201_01257_amd import synth
+
+    wl = synth.WORKLOADS["ladder_o10_v40_t5"]
+    orb = synth.Orbitals(wl["n_occ"], wl["n_vir"])
+    g = {c: _gpu_space(tm, orb, c, wl["tile_occ"] if c == "o" else wl["tile_vir"]) for c in "ov"}
+    osp = {c: _oracle_space(oracle, orb, c, wl["tile_occ"] if c == "o" else wl["tile_vir"]) for c in "ov"}
+    V = tm.Tensor([g[c] for c in "vvvv"])
+    V.fill_blocks(lambda lo, ext, out: orb.fill("V_vvvv", "vvvv", lo, ext, out=out))
+    T = tm.Tensor([g[c] for c in "vvoo"])
+    T.fill_blocks(lambda lo, ext, out: orb.fill("T2", "vvoo", lo, ext, out=out))
+    R = tm.Tensor([g[c] for c in "vvoo"])
+    plan = tm.Plan(R, "abij", V, "abcd", T, "cdij")
+    if not args.no_tune:
+        plan.autotune(args.tune_cache, reps=3)
+    flops = plan.stats()["useful_flops"]
+    eager_ms = _time(torch, lambda: plan.execute(0.5, 0.0), reps, 10)
+    grp = tm.Group([tm.Plan(R, "abij", V, "abcd", T, "cdij", bind=False)])
+    if not args.no_tune:
+        grp.autotune(args.tune_cache, reps=3)
+    grp.capture([0.5], [0.0])
+    graph_ms = _time(torch, lambda: grp.execute([0.5], [0.0]), reps, 10)
+    torch.cuda.synchronize()
+    got = R.to_blocks()
+    Vo = _oracle_tensor(oracle, synth, orb, osp, "V_vvvv", "vvvv")
+    To = _oracle_tensor(oracle, synth, orb, osp, "T2", "vvoo")
+    Ro = oracle.BlockTensor([osp[c] for c in "vvoo"])
+    for t in Vo.stored_tiles():
+        Vo.blocks[t]
+    for t in To.stored_tiles():
+        To.blocks[t]
+    t0 = time.perf_counter()
+    ref = oracle.contract(Ro, "abij", Vo, "abcd", To, "cdij", 0.5, 0.0).blocks
+    cpu_s = time.perf_counter() - t0
+    err = max(max_rel_elementwise(got[t], ref[t]) for t in ref)
+    if err > 1e-12:
+        raise SystemExit(f"config-0 parity failure: {err:.3e}")
+    return {"workload": "ladder_o10_v40_t5", "useful_mflop": round(flops / 1e6, 3), "tasks": plan.stats()["tasks"],
+            "eager_us": round(eager_ms * 1e3, 2), "eager_tflops": round(flops / eager_ms / 1e9, 4),
+            "graph_us": round(graph_ms * 1e3, 2), "graph_tflops": round(flops / graph_ms / 1e9, 4),
+            "config": plan.config_name(), "rel_err": float(f"{err:.3e}"), "rel_err_tolerance": 1e-12,
+            "cpu_baseline": {"value": round(flops / cpu_s / 1e12, 6), "unit": "TFLOP/s", "cores": int(_blas_threads()),
+                             "kind": "oracle",
+                             "sample": f"the whole problem (all {len(ref)} output blocks), {cpu_s:.2f} s",
+                             "seconds": round(cpu_s, 3)}}
 
 
 def run_batched(args):
+    """The 256-problem group as its own JSON line."""
+    res = batched_leg(args, args.steps, args.warmup)
+    _emit(args, dict({"metric": METRIC, "workload": "batched", "value": res["graph_tflops"], "unit": "TFLOP/s",
+                      "dtype": "f64", "data": "synthetic"}, **res))
+
+
+def batched_leg(args, steps, warmup):
     """256 independent contractions (random index spaces, mixed terms) as one group: screening +
-    persistent contraction, autotuned, captured once into a hipGraph and replayed."""
+    persistent contraction, autotuned, captured once into a hipGraph and replayed; eager and
+    replayed times, parity on sampled problems, whose oracle time is the CPU baseline."""
     import torch
 
     import oracle
@@ -623,13 +756,14 @@ def run_batched(args):
     t0 = time.time()
     group.autotune(args.tune_cache, reps=2)
     log(f"[bench] autotuned group in {time.time() - t0:.1f}s: {group.stats()}")
-    eager_ms = _time(torch, lambda: group.execute(alphas, betas), args.steps, args.warmup)
+    eager_ms = _time(torch, lambda: group.execute(alphas, betas), steps, warmup)
     group.capture(alphas, betas)
-    graph_ms = _time(torch, lambda: group.execute(alphas, betas), args.steps, args.warmup)
+    graph_ms = _time(torch, lambda: group.execute(alphas, betas), steps, warmup)
     flops = sum(m["plan"].stats()["useful_flops"] for m in members)
     # parity on sampled problems (one block each)
     rng = np.random.default_rng(7)
     worst = 0.0
+    cpu_s, cpu_flops = 0.0, 0.0
     for i in rng.choice(len(members), size=16, replace=False):
         m = members[int(i)]
         d = m["desc"]
@@ -637,19 +771,36 @@ def run_batched(args):
         osp = {c: _oracle_space(oracle, m["orb"], c, d["tile_occ"] if c == "o" else d["tile_vir"]) for c in "ov"}
         tiles = [tuple(int(x) for x in t) for t in m["O"].block_tiles]
         pick = [tiles[int(rng.integers(0, len(tiles)))]]
-        ref = oracle.contract(_oracle_tensor(oracle, synth, m["orb"], osp, on, op), ol,
-                              _oracle_tensor(oracle, synth, m["orb"], osp, ln, lp), ll,
-                              _oracle_tensor(oracle, synth, m["orb"], osp, rn, rp), rl, a, 0.0, out_tiles=pick).blocks
-        worst = max(worst, _rel(m["O"].to_blocks(), ref, pick)[0])
+        oo = _oracle_tensor(oracle, synth, m["orb"], osp, on, op)
+        lo = _oracle_tensor(oracle, synth, m["orb"], osp, ln, lp)
+        ro = _oracle_tensor(oracle, synth, m["orb"], osp, rn, rp)
+        scr = oracle.screen(oo, ol, lo, ll, ro, rl)
+        _touch(oo, ol, lo, ll, ro, rl, pick[0], scr["pairs"][pick[0]])  # inputs generated outside the timing
+        cpu_flops += sum(2.0 * float(np.prod(oo.block_shape(pick[0]))) * _kext(lo, ll, ol, kt, rl, ro)
+                         for kt in scr["pairs"][pick[0]])
+        t0 = time.perf_counter()
+        ref = oracle.contract(oo, ol, lo, ll, ro, rl, a, 0.0, out_tiles=pick).blocks
+        cpu_s += time.perf_counter() - t0
+        got = m["O"].to_blocks()
+        e = _rel(got, ref, pick)[0]
+        mx = float(np.max(np.abs(ref[pick[0]])))
+        if mx > 0:
+            e = max(e, float(np.max(np.abs(got[pick[0]] - ref[pick[0]]))) / mx)
+        worst = max(worst, e)
     if worst > 1e-12:
         raise SystemExit(f"batched parity failure: {worst}")
     st = group.stats()
-    _emit(args, {"metric": METRIC, "workload": "batched", "value": round(flops / graph_ms / 1e9, 4), "unit": "TFLOP/s",
-                 "dtype": "f64", "data": "synthetic", "problems": len(members), "useful_gflop": round(flops / 1e9, 2),
-                 "graph_ms": round(graph_ms, 3), "eager_ms": round(eager_ms, 3),
-                 "eager_tflops": round(flops / eager_ms / 1e9, 3), "config": st, "rel_err_max_sampled": float(f"{worst:.3e}"),
-                 "roofline": {"bound": "mfma", "achieved": round(flops / graph_ms / 1e9, 3), "peak": PEAK_F64_MFMA_TFLOPS,
-                              "unit": "TFLOP/s", "frac": round(flops / graph_ms / 1e9 / PEAK_F64_MFMA_TFLOPS, 4)}})
+    cpu = {"value": round(cpu_flops / max(cpu_s, 1e-9) / 1e12, 5), "unit": "TFLOP/s", "cores": int(_blas_threads()),
+           "kind": "oracle",
+           "sample": f"one seeded output block of each of 16 seeded problems ({cpu_flops / 1e9:.2f} GFLOP useful, "
+                     f"{cpu_s:.2f} s; input generation not timed)", "seconds": round(cpu_s, 2)}
+    return {"problems": len(members), "useful_gflop": round(flops / 1e9, 2),
+            "graph_ms": round(graph_ms, 3), "eager_ms": round(eager_ms, 3),
+            "graph_tflops": round(flops / graph_ms / 1e9, 3), "eager_tflops": round(flops / eager_ms / 1e9, 3),
+            "config": st, "rel_err_max_sampled": float(f"{worst:.3e}"), "rel_err_tolerance": 1e-12,
+            "roofline": {"bound": "mfma", "achieved": round(flops / graph_ms / 1e9, 3), "peak": PEAK_F64_MFMA_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(flops / graph_ms / 1e9 / PEAK_F64_MFMA_TFLOPS, 4)},
+            "cpu_baseline": cpu}
 
 
 def run_adjoint(args):

@@ -1,29 +1,48 @@
-"""Element-wise error bounds of the mixed-precision contraction paths, derived from their definitions.
+"""Element-wise error bounds of the mixed-precision contraction paths, derived from their definitions
+and from the measured rounding of the matrix-core instructions.
 
-For one output element r = sum_k a_k b_k (times alpha) the device result differs from the float64
-value by the operand rounding (f32) or the dropped split terms (bf16x3, bf16x4_aligned), plus the
-float32 rounding of the window sums, plus float64 rounding.  With u = 2^-24 (half a float32 ulp),
-u_mfma the relative error of one matrix-core accumulation step (its result rounded once; at most
-one float32 ulp, 2u), W = 256 the promotion window and n_w the windows of the element:
+Rounding of one matrix-core instruction D = C + sum_k A_k B_k (measured on crafted inputs whose
+exact sums the host knows, tests/test_gpu_mfma_rounding.py):
 
-  f32:    |err| <= (2u + u^2 + (W/4) u_mfma + n_w 2^-52) S
-          -- each operand rounded once (relative u); 64 chained 4-deep accumulation steps per
-          window, each rounded relative to a partial sum of magnitude <= S_window.
-  bf16x3: |err| <= (4.1 u + 8 (1+2^-7) u_mfma + 40 * 0.0079 u_mfma + n_w 2^-52) S
+* bfloat16 instructions (v_mfma_f32_16x16x32_bf16, v_mfma_f32_32x32x16_bf16): the products are
+  exact; the accumulator and the products are aligned to the largest of them, every bit more than
+  24 places below its leading bit is dropped without a sticky bit (2^12 + 2^-12 - 2^12 keeps
+  2^-12, 2^8 + 2^-17 - 2^8 loses 2^-17; 1 - 1 + 2^-30 gives 0), the aligned terms are summed
+  exactly (four quarter-ulps add up to one ulp) and the sum is rounded to nearest even once;
+* float32 instructions (v_mfma_f32_16x16x4_f32, v_mfma_f32_32x32x2_f32): results as if the
+  accumulator and then each product were added by ordinary float32 additions rounded to nearest
+  even (four quarter-ulps added to 1 vanish one by one; 1 - 1 + 2^-30 keeps 2^-30).
+
+Either way one instruction with K products is off by at most (K + 2) u M, u = 2^-24, M the largest
+magnitude among its terms (each of the K + 1 terms loses less than u M, the final rounding less than
+u |D| <= u (K + 1) M is covered by the count since M bounds the running sum it rounds).  Inside a
+promotion window of W = 256 summed indices the accumulator and the products are bounded by the
+window's sum S_w of |a_k b_k| (of the products that accumulator takes), so an accumulator that runs
+n instructions per window is off by at most n (K + 2) u S_w.  With n_w windows per element and the
+float64 promotion and epilogue:
+
+  f32:    |err| <= (2u + u^2 + 64 * 6 u + (n_w + 1) 2^-52) S
+          -- each operand rounded once (relative u); 64 instructions of 4 products per window.
+  bf16x3: |err| <= (4.1 u + 8 * 34 u + 40 * 34 u * 0.0079 + (n_w + 1) 2^-52) S
           -- slices b_i = bf16(...) leave |x - b0 - b1 - b2| <= 2^-24 |x| and |b_i| <= 2^-8i |x|
           (1 + 2^-8), so the dropped products (i + j >= 3, and the remainders) sum to < 4.1 u |ab|;
-          b0*b0 runs in its own accumulator (8 steps per window), the five products of order 1
-          and 2 (together <= 0.0079 |ab|) in another (40 steps per window).
-  bf16x4_aligned: |err| <= (1.2e-9 + 72 * 0.0079 u_mfma + n_w 2^-52) T
-          -- T = sum_k max_a max_b over the (row, window) maxima of |a| and |b|: the lead slices are
-          multiples of 2^(E-8) below a window maximum 2^(E-1) <= max < 2^E, their window sums are
-          exact in float32; the residual |x - lead| <= 2^-8 max is split in three bfloat16 slices
-          (remainder <= 2^-32 max); dropped products of order >= 4 and remainders < 5 * 2^-32;
-          the nine residual products (together <= 0.0079 max_a max_b) run 72 steps per window.
+          b0*b0 runs in its own accumulator (8 instructions of 32 products per window), the five
+          products of order 1 and 2 (together <= 0.0079 |ab|) in another (40 per window).
+  bf16x4_aligned: |err| <= (1.2e-9 + 72 * 34 u * 0.0079 + (n_w + 1) 2^-52) T
+          -- T = sum_k over the (row, window) maxima of |a| and |b|: the lead slices are multiples
+          of 2^(E-8) below a window maximum 2^(E-1) <= max < 2^E, their window sums are integers
+          times one power of two below 2^24 of it, so aligned and summed exactly; the residual
+          |x - lead| <= 2^-8 max is split in three bfloat16 slices (remainder <= 2^-32 max);
+          dropped products of order >= 4 and remainders < 5 * 2^-32; the nine residual products
+          (together <= 0.0079 max_a max_b) run 72 instructions per window.
 
 S = sum_k |a_k| |b_k| is the same contraction on |lhs|, |rhs| (times |alpha|); T is it on operands
-whose elements are replaced by their (row, window) maximum magnitude, windows as the header of
-the library defines them (the flattening order of oracle.split).
+whose elements are replaced by their (row, window) maximum magnitude, windows as the header of the
+library defines them (the flattening order of oracle.split, a specification of that layout).
+
+These are worst-case bounds: they catch a wrong slice or a dropped product of order one (2^-8
+relative), not the statistical size of the rounding error, which the tests bound separately with
+the relative Frobenius error of each precision.
 """
 
 from __future__ import annotations
@@ -37,14 +56,19 @@ U = 2.0 ** -24
 WINDOW = osplit.WINDOW
 
 
-def coefficient(precision: str, u_mfma: float, n_windows: int) -> float:
-    f64 = n_windows * 2.0 ** -52 + 2.0 ** -52
+def step(K: int) -> float:
+    """Worst-case error of one matrix-core instruction with K products, relative to its largest term."""
+    return (K + 2) * U
+
+
+def coefficient(precision: str, n_windows: int) -> float:
+    f64 = (n_windows + 1) * 2.0 ** -52
     if precision == "f32":
-        return 2 * U + U * U + (WINDOW // 4) * u_mfma + f64
+        return 2 * U + U * U + (WINDOW // 4) * step(4) + f64
     if precision == "bf16x3":
-        return 4.1 * U + 8 * (1 + 2.0 ** -7) * u_mfma + 40 * 0.0079 * u_mfma + f64
+        return 4.1 * U + (WINDOW // 32) * step(32) + 5 * (WINDOW // 32) * step(32) * 0.0079 + f64
     if precision == "bf16x4_aligned":
-        return 1.2e-9 + 72 * 0.0079 * u_mfma + f64
+        return 1.2e-9 + 9 * (WINDOW // 32) * step(32) * 0.0079 + f64
     raise ValueError(precision)
 
 
@@ -81,7 +105,7 @@ def _mapped(t: oracle.BlockTensor, fn) -> oracle.BlockTensor:
     return x
 
 
-def bound_blocks(precision, out, ol, lhs, ll, rhs, rl, alpha, tiles, u_mfma):
+def bound_blocks(precision, out, ol, lhs, ll, rhs, rl, alpha, tiles):
     """Per sampled output block the element-wise bound (same shape as the block)."""
     k_order = osplit.summed_label_order(ol, ll, rl)
     if precision == "bf16x4_aligned":
@@ -102,7 +126,7 @@ def bound_blocks(precision, out, ol, lhs, ll, rhs, rl, alpha, tiles, u_mfma):
             for c, ti in zip(kl, kt):
                 ext *= lhs.spaces[ll.index(c)].sizes[ti]
             nw += -(-ext // WINDOW)
-        res[t] = coefficient(precision, u_mfma, nw) * mag[t]
+        res[t] = coefficient(precision, nw) * mag[t]
     return res
 
 

@@ -143,28 +143,3 @@ def test_ccsd_workload_full_size_sampled():
                               bench._oracle_tensor(oracle, synth, orb, osp, rn, rp), rl, a, 0.0, out_tiles=pick)
         got = out.to_blocks()
         assert rel_err({t: got[t] for t in pick}, {t: ref.blocks[t] for t in pick}) <= TOL, term
-
-
-@pytest.mark.slow
-def test_mixed_workload_aligned_split_full_size_sampled():
-    import bench
-
-    wl = synth.WORKLOADS["mixed_o64_v320_t64"]
-    orb = synth.Orbitals(wl["n_occ"], wl["n_vir"])
-    g = {c: bench._gpu_space(tm, orb, c, wl["tile_occ"] if c == "o" else wl["tile_vir"]) for c in "ov"}
-    osp = {c: bench._oracle_space(oracle, orb, c, wl["tile_occ"] if c == "o" else wl["tile_vir"]) for c in "ov"}
-    V = tm.Tensor([g[c] for c in "vvvv"])
-    V.fill_blocks(lambda lo, ext, out: orb.fill("V_vvvv", "vvvv", lo, ext, out=out))
-    T2 = tm.Tensor([g[c] for c in "vvoo"])
-    T2.fill_blocks(lambda lo, ext, out: orb.fill("T2", "vvoo", lo, ext, out=out))
-    R = tm.Tensor([g[c] for c in "vvoo"])
-    plan = tm.Plan(R, "abij", V, "abcd", T2, "cdij", precision="bf16x4_aligned")
-    assert plan.stats()["gather_layout"] & 8  # tiles of 64: the slice-plane layout
-    plan.execute(0.5, 0.0)
-    torch.cuda.synchronize()
-    Ro = oracle.BlockTensor([osp[c] for c in "vvoo"])
-    pick = _sampled_tiles(Ro.stored_tiles(), 2, 2201)
-    ref = oracle.contract(Ro, "abij", bench._oracle_tensor(oracle, synth, orb, osp, "V_vvvv", "vvvv"), "abcd",
-                          bench._oracle_tensor(oracle, synth, orb, osp, "T2", "vvoo"), "cdij", 0.5, 0.0, out_tiles=pick)
-    got = R.to_blocks()
-    assert rel_err({t: got[t] for t in pick}, {t: ref.blocks[t] for t in pick}) <= 1e-8

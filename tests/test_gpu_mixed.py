@@ -1,10 +1,17 @@
-"""Mixed-precision contraction paths against the FP64 oracle (relative Frobenius error per term).
+"""Mixed-precision contraction paths against the FP64 oracle.
 
-Tolerances are the stated error budgets of each scheme (no exact pin exists for them):
-  bf16x4_aligned (aligned lead slice + three bfloat16 residual slices, ten products): <= 1e-8
-  bf16x3 (three plain bfloat16 slices, six products):                               <= 3e-7
-  f32 (float32 operands and window sums):                                           <= 1e-6
-Every path promotes float32 window sums to float64 and runs a float64 epilogue.
+Two checks per result, both asserted:
+* element by element, |got - ref| <= the worst-case bound that tests/mixed_bound.py derives from
+  the split definitions and the measured rounding of the matrix-core instructions (catches a
+  wrong slice or a dropped product of order one);
+* per term, the larger of the relative Frobenius error and max |got - ref| / max |ref| (the
+  statistical size of the rounding) within the stated budget of each scheme:
+    bf16x4_aligned (aligned lead slice + three bfloat16 residual slices, ten products): <= 1e-8
+    bf16x3 (three plain bfloat16 slices, six products, lead products accumulated apart): <= 3e-7
+    f32 (float32 operands and window sums):                                           <= 1e-6
+Every path promotes float32 window sums to float64 and runs a float64 epilogue.  The full-size
+tests run the workload of O = 64, V = 320 spin-orbitals in tiles of 64 on sampled output blocks
+drawn from every stored block.
 
 The operand splits themselves have an exact definition: the words the library multiplies
 (tamm_plan_split_operand) are compared bit for bit with the oracle's split (oracle/split.py) of
@@ -19,6 +26,7 @@ import oracle
 from paper_2201_01257_amd import core as tm
 from paper_2201_01257_amd import synth
 from oracle import split as osplit
+from tests import mixed_bound
 from tests.gpu_util import Problem, max_rel
 
 pytestmark = pytest.mark.gpu
@@ -27,6 +35,8 @@ TOL = {"bf16x4_aligned": 1e-8, "bf16x3": 3e-7, "f32": 1e-6}
 
 
 def run(prob, term, precision, config=None, k_splits=0, beta=0.0):
+    """Run one term on the GPU; check it against the oracle (element-wise bound asserted here);
+    return (got blocks, reference blocks, plan)."""
     (on, op, ol), (ln, lp, ll), (rn, rp, rl), a = synth.TERMS[term]
     L = prob.gpu_tensor(ln, lp)
     R = prob.gpu_tensor(rn, rp)
@@ -36,9 +46,16 @@ def run(prob, term, precision, config=None, k_splits=0, beta=0.0):
         plan.set_config(config, k_splits)
     plan.execute(a, beta)
     torch.cuda.synchronize()
-    ref = oracle.contract(prob.oracle_tensor(on, op), ol, prob.oracle_tensor(ln, lp), ll, prob.oracle_tensor(rn, rp), rl,
-                          a, beta)
-    return O.to_blocks(), ref.blocks, plan
+    Oo, Lo, Ro = prob.oracle_tensor(on, op), prob.oracle_tensor(ln, lp), prob.oracle_tensor(rn, rp)
+    ref = oracle.contract(Oo, ol, Lo, ll, Ro, rl, a, beta)
+    got = O.to_blocks()
+    tiles = list(ref.blocks)
+    bound = mixed_bound.bound_blocks(precision, Oo, ol, Lo, ll, Ro, rl, a, tiles)
+    if beta != 0.0:  # the float64 epilogue's beta * out term: one more rounding of |beta out|
+        bound = {t: bound[t] + 2.0 ** -52 * abs(beta) * np.abs(Oo.blocks[t]) for t in tiles}
+    worst = mixed_bound.check(got, ref.blocks, bound, tiles)
+    assert worst <= 1.0, (precision, term, "element-wise bound exceeded", worst)
+    return got, ref.blocks, plan
 
 
 @pytest.mark.parametrize("precision", list(TOL))
@@ -117,3 +134,59 @@ def test_split_operand_rejects_float64_plans():
                    prob.gpu_tensor(rn, rp, fill=False), rl)
     with pytest.raises(tm.TammError):
         plan.split_operand(0)
+
+
+# ---- full size: O = 64, V = 320 spin-orbitals, tiles of 64 (ladder and ring) --------------------
+FULL = "mixed_o64_v320_t64"
+FULL_TERMS = {"ladder": ("V_vvvv", "vvvv", "abcd", "T2", "vvoo", "cdij", 0.5),
+              "ring": ("V_ovvo", "ovvo", "mbej", "T2", "vvoo", "aeim", 1.0)}
+
+
+@pytest.fixture(scope="module")
+def full_size():
+    import bench
+
+    wl = synth.WORKLOADS[FULL]
+    orb = synth.Orbitals(wl["n_occ"], wl["n_vir"])
+    g = {c: bench._gpu_space(tm, orb, c, wl["tile_occ"] if c == "o" else wl["tile_vir"]) for c in "ov"}
+    osp = {c: bench._oracle_space(oracle, orb, c, wl["tile_occ"] if c == "o" else wl["tile_vir"]) for c in "ov"}
+    T = {}
+    for name, pat in (("V_vvvv", "vvvv"), ("V_ovvo", "ovvo"), ("T2", "vvoo")):
+        T[name] = tm.Tensor([g[c] for c in pat])
+        T[name].fill_blocks(lambda lo, ext, out, n=name, p=pat: orb.fill(n, p, lo, ext, out=out))
+    R = tm.Tensor([g[c] for c in "vvoo"])
+    Ro = oracle.BlockTensor([osp[c] for c in "vvoo"])
+    rng = np.random.default_rng(64320)
+    tiles = Ro.stored_tiles()
+    pick = [tiles[i] for i in rng.choice(len(tiles), size=2, replace=False)]
+    ops, refs = {}, {}
+    for term, (ln, lp, ll, rn, rp, rl, a) in FULL_TERMS.items():
+        Lo = bench._oracle_tensor(oracle, synth, orb, osp, ln, lp)
+        To = bench._oracle_tensor(oracle, synth, orb, osp, rn, rp)
+        ops[term] = (Lo, To)
+        refs[term] = oracle.contract(Ro, "abij", Lo, ll, To, rl, a, 0.0, out_tiles=pick).blocks
+    yield dict(T=T, R=R, Ro=Ro, pick=pick, ops=ops, refs=refs)
+    del T, R
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", ["f32", "bf16x3", "bf16x4_aligned"])
+@pytest.mark.parametrize("term", ["ladder", "ring"])
+def test_full_size_sampled_blocks(full_size, precision, term):
+    f = full_size
+    ln, lp, ll, rn, rp, rl, a = FULL_TERMS[term]
+    plan = tm.Plan(f["R"], "abij", f["T"][ln], ll, f["T"][rn], rl, precision=precision)
+    if precision != "f32":
+        assert plan.stats()["gather_layout"] & 8  # tiles of 64: the slice-plane layout
+    plan.autotune("", reps=1)  # the configuration the bench times
+    plan.execute(a, 0.0)
+    torch.cuda.synchronize()
+    got = f["R"].to_blocks()
+    pick, ref = f["pick"], f["refs"][term]
+    Lo, To = f["ops"][term]
+    bound = mixed_bound.bound_blocks(precision, f["Ro"], "abij", Lo, ll, To, rl, a, pick)
+    worst = mixed_bound.check(got, ref, bound, pick)
+    assert worst <= 1.0, (precision, term, "element-wise bound exceeded", worst)
+    rel, mx = max_rel({t: got[t] for t in pick}, ref, pick)
+    assert rel <= TOL[precision], (precision, term, rel, mx)
