@@ -290,6 +290,22 @@ int tamm_contract(tamm_tensor* out, const char* out_lbl, const tamm_tensor* lhs,
 int tamm_contract_cache_count(int64_t* plans);
 int tamm_contract_cache_clear(void);
 
+/* For callers that cannot allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): tamm_contract with no workspace argument.  The workspace is a
+ * file-scope device array of the library, tamm_contract_noalloc_max_workspace() bytes (64 MiB) on
+ * each GPU the library runs on, held until the process ends; the call allocates nothing (no
+ * hipMalloc, no library allocation).  Same operation, arguments, plan cache and results as
+ * tamm_contract on the current device; the stream must belong to that device.  ERR_WORKSPACE,
+ * before anything is enqueued, when the contraction needs more workspace than the array holds
+ * (host check, tamm_contract_workspace_size).  All calls on one GPU share its array, which keeps
+ * the last call's contents (nothing in it needs to start zeroed); calls that overlap in time on one
+ * GPU race on it and must be serialised by the caller.  Switching the array between contractions
+ * re-uploads the plan tables after draining the device, as tamm_contract does. */
+int tamm_contract_noalloc(tamm_tensor* out, const char* out_lbl, const tamm_tensor* lhs, const char* lhs_lbl,
+                          const tamm_tensor* rhs, const char* rhs_lbl, int32_t precision, double alpha, double beta,
+                          void* stream);
+size_t tamm_contract_noalloc_max_workspace(void);
+
 /* ------------------------------------------------------------------------------------------
  * Groups: many independent plans executed together (the single-GPU analogue of running the
  * operations of one scheduler level at once, Sec. III-B): one screening launch over every

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtamm_mi.so")
 SOURCES = ["capi_core.cpp", "plan.cpp", "denominator.cpp", "addop.cpp", "sched.cpp", "cholesky.cpp", "kernels.hip", "kernels_mixed.hip",
-           "kernels_elem.hip", "diag.hip"]
+           "kernels_elem.hip", "diag.hip", "noalloc.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",

@@ -403,6 +403,16 @@ def contract(out: Tensor, ol: str, lhs: Tensor, ll: str, rhs: Tensor, rl: str, a
     return out
 
 
+def contract_noalloc(out: Tensor, ol: str, lhs: Tensor, ll: str, rhs: Tensor, rl: str, alpha: float = 1.0,
+                     beta: float = 0.0, precision: str = "f64", stream=None) -> Tensor:
+    """out(ol) = beta*out(ol) + alpha * lhs(ll) * rhs(rl) through tamm_contract_noalloc: no
+    workspace argument and no device allocation (the library's per-GPU scratch array).  Returns ``out``."""
+    s = current_stream_handle() if stream is None else stream
+    check(load().tamm_contract_noalloc(out._h, ol.encode(), lhs._h, ll.encode(), rhs._h, rl.encode(),
+                                       PRECISIONS[precision], float(alpha), float(beta), s))
+    return out
+
+
 def contract_cache_count() -> int:
     """Number of one-shot plans in the library's cache."""
     n = ctypes.c_int64()

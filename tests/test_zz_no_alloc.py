@@ -1,0 +1,47 @@
+"""The allocation-free one-shot contraction (tamm_contract_noalloc) against the one-shot contraction
+with a caller workspace (tamm_contract) and the oracle: two calls in a row on the GPU, the second
+with a smaller problem, each bitwise equal to tamm_contract on the same inputs and within 1e-12
+(element-wise and Frobenius) of the oracle; a contraction needing more than the scratch array is
+rejected on the host before anything runs."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2201_01257_amd import _lib
+from paper_2201_01257_amd import core as tm
+from tests.gpu_util import Problem, max_rel
+
+
+@pytest.mark.gpu
+def test_noalloc_matches_caller_workspace_twice_second_smaller():
+    for shape in [(12, 40, 6, 10), (8, 22, 4, 5)]:
+        prob = Problem(*shape)
+        V = prob.gpu_tensor("V_vvvv", "vvvv")
+        T = prob.gpu_tensor("T2", "vvoo")
+        R1 = prob.gpu_tensor(None, "vvoo", fill=False)
+        R2 = prob.gpu_tensor(None, "vvoo", fill=False)
+        R1.data.fill_(float("nan"))  # beta = 0 never reads out
+        tm.contract_noalloc(R1, "abij", V, "abcd", T, "cdij", 0.5, 0.0)
+        tm.contract(R2, "abij", V, "abcd", T, "cdij", 0.5, 0.0)
+        torch.cuda.synchronize()
+        got, want = R1.to_blocks(), R2.to_blocks()
+        for k in want:
+            assert np.array_equal(got[k], want[k]), (shape, k)
+        ref = oracle.contract(oracle.BlockTensor.zeros([prob.o[c] for c in "vvoo"]), "abij",
+                              prob.oracle_tensor("V_vvvv", "vvvv"), "abcd", prob.oracle_tensor("T2", "vvoo"), "cdij",
+                              0.5, 0.0)
+        rel, mx = max_rel(got, ref.blocks)
+        assert rel <= 1e-12, (shape, rel, mx)
+
+
+def test_noalloc_rejects_a_workspace_beyond_the_scratch_array():
+    m = tm.Space.fixed(64, 1)
+    k = tm.Space.fixed(2048, 1)
+    C, A, B = tm.Tensor([m, m], device=None), tm.Tensor([m, k], device=None), tm.Tensor([k, m], device=None)
+    need = tm.Plan(C, "ij", A, "ik", B, "kj", bind=False).workspace_size()
+    assert need > _lib.load().tamm_contract_noalloc_max_workspace()
+    with pytest.raises(tm.TammError) as e:
+        tm.contract_noalloc(C, "ij", A, "ik", B, "kj", 1.0, 0.0, stream=None if torch.cuda.is_available() else 0)
+    assert e.value.status == "TAMM_ERR_WORKSPACE"
