@@ -197,6 +197,9 @@ typedef struct {
                              precisions store the split operands as slice planes, each block
                              [row][k], because every operand block's K extent is a multiple
                              of 8 (16-byte gathers of 8 slices)                              */
+  int32_t xcd_chunk;      /* launch order over the eight dies: work items per die chunk (0: the
+                             plain longest-first order); see tamm_plan_set_order                */
+  int32_t tile_order;     /* 0: the tiles of a block row by row; 1: grouped by B column panel  */
   int32_t reserved;       /* zero                                                              */
 } tamm_plan_stats;
 
@@ -210,12 +213,30 @@ int tamm_plan_stats_get(const tamm_plan* p, tamm_plan_stats* s);
  * re-querying the workspace size and re-binding. */
 int tamm_plan_config_count(const tamm_plan* p, int32_t* count);
 int tamm_plan_set_config(tamm_plan* p, int32_t config, int32_t k_splits);
+/* Launch order of the work items (results do not depend on it, bit for bit).  The list is
+ * longest first; among tiles of equal cost, tile_order 0 keeps the tiles of one output block
+ * together, row by row (neighbours share A row panels), and tile_order 1 groups the tiles that
+ * read the same B column panel across blocks and rows.  Then the list is cut into chunks of
+ * `chunk` items for the chip's eight dies (each with its own L2), chunk c running on die c mod 8;
+ * 0 keeps the list as it is; -1 restores the library default (32, or the TAMM_XCD_CHUNK
+ * environment variable).  The autotuner searches both after the kernel configuration.  Requires
+ * re-binding. */
+int tamm_plan_set_order(tamm_plan* p, int32_t tile_order, int32_t chunk);
+/* Declare operand `which` (0 = lhs, 1 = rhs) constant (constant != 0) or variable.  For the
+ * split-bfloat16 precisions the split of a constant operand, made by the first execution, is
+ * reused by later executions as long as the operand stays bound to the same storage and the
+ * workspace is not re-bound; the caller promises not to change its values meanwhile (integrals
+ * during coupled-cluster iterations, for example).  Calling it again (either value) forces a new
+ * split at the next execution, after the caller changed the values.  No effect on other
+ * precisions.  Host only. */
+int tamm_plan_set_constant(tamm_plan* p, int32_t which, int32_t constant);
 /* Human-readable name of a configuration (static string), e.g. "f64_m128n64k16_w2x2_o1". */
 const char* tamm_config_name(int32_t precision, int32_t config);
 
 /* Autotuner.  Measures every kernel configuration with K splits 1, 2, 4 and 8 that fits the
  * given workspace (hipEvents on stream; after one warm-up, the fastest of `reps` individually
- * timed executions counts; reps <= 0 means 3), keeps the fastest, and leaves the plan configured
+ * timed executions counts; reps <= 0 means 3), then both tile orders with die chunks of 0, 16, 32,
+ * 64 and 128 items (tamm_plan_set_order) for the fastest, keeps the fastest, and leaves the plan configured
  * and bound to `workspace`.  With K splits s > 1 the tiles of the blocks with the largest summed
  * K extent are split into s parts and lighter blocks' tiles into proportionally fewer (at least
  * one), so the parts cost about the same.  The

@@ -29,6 +29,8 @@ class PlanStats(ctypes.Structure):
         ("kernel_config", c_i32),
         ("k_splits", c_i32),
         ("gather_layout", c_i32),
+        ("xcd_chunk", c_i32),
+        ("tile_order", c_i32),
         ("reserved", c_i32),
     ]
 
@@ -54,6 +56,8 @@ SIGNATURES = {
     "tamm_plan_stats_get": (c_int, [c_vp, P(PlanStats)]),
     "tamm_plan_config_count": (c_int, [c_vp, P(c_i32)]),
     "tamm_plan_set_config": (c_int, [c_vp, c_i32, c_i32]),
+    "tamm_plan_set_order": (c_int, [c_vp, c_i32, c_i32]),
+    "tamm_plan_set_constant": (c_int, [c_vp, c_i32, c_i32]),
     "tamm_config_name": (c_char_p, [c_i32, c_i32]),
     "tamm_plan_autotune_workspace_size": (c_int, [c_vp, P(c_size_t)]),
     "tamm_plan_autotune": (c_int, [c_vp, c_vp, c_size_t, c_vp, c_char_p, c_i32]),

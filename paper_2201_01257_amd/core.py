@@ -324,6 +324,18 @@ class Plan:
         if self.out.data is not None:
             self.bind_workspace()
 
+    def set_constant(self, which: int, constant: bool = True):
+        """Declare operand ``which`` (0 = lhs, 1 = rhs) constant: its split-bfloat16 slices are made
+        once and reused (tamm_plan_set_constant); call again after changing its values."""
+        check(load().tamm_plan_set_constant(self._h, int(which), 1 if constant else 0))
+
+    def set_order(self, tile_order: int = 0, chunk: int = -1):
+        """Launch order: tile order (0 row by row per block, 1 grouped by B column panel) and work
+        items per die chunk (0: none, -1: library default); see tamm_plan_set_order."""
+        check(load().tamm_plan_set_order(self._h, int(tile_order), int(chunk)))
+        if self.out.data is not None:
+            self.bind_workspace()
+
     def autotune(self, cache_path: str = "", reps: int = 3, stream=None):
         """Measure the kernel configurations and keep the fastest (see tamm_plan_autotune)."""
         n = ctypes.c_size_t()

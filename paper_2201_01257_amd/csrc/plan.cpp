@@ -108,9 +108,16 @@ struct tamm_plan {
   // split-bfloat16 precisions: per stored operand block, the split work description
   std::vector<PrepBlock> prepA, prepB;
   int64_t prepA_items = 0, prepB_items = 0;
+  // operands the caller declared constant (tamm_plan_set_constant): their split is reused while
+  // it is valid -- taken from the same storage into the current workspace
+  bool const_A = false, const_B = false;
+  const void* split_src_A = nullptr;  // storage the split of A in the workspace was taken from
+  const void* split_src_B = nullptr;
   // kernel configuration and work decomposition
   int config = -1;
   int k_splits = 1;
+  int xcd_chunk = -1;              // work items per die chunk (xcd_order); -1: the library default
+  int tile_order = 0;              // 0: tiles of a block row by row; 1: grouped by B column panel
   std::vector<WorkItem> work;
   std::vector<ReduceItem> reduce;
   tamm_plan_stats stats{};
@@ -651,17 +658,34 @@ static int configure_work(tamm_plan* p, int config, int k_splits) {
     }
     if (slots > INT32_MAX / 2) return fail(TAMM_ERR_UNSUPPORTED, "too many partial tiles");
   }
-  // longest processing time first; the parts of a tile stay adjacent when their costs tie
-  std::stable_sort(parts.begin(), parts.end(), [](const Part& x, const Part& y) { return x.cost > y.cost; });
+  // longest processing time first; the parts of a tile stay adjacent when their costs tie.  Order
+  // 0 keeps the tiles of one block row by row (neighbours share A row panels); order 1 puts the
+  // tiles that read the same B column panel -- the same N tiles of their blocks, the same first
+  // column -- next to each other across the blocks and rows (for operations whose B panels are the
+  // large ones, such as a few output rows against long columns)
+  const std::vector<OutBlockDesc>& bd = p->blocks;
+  if (p->tile_order == 1)
+    std::stable_sort(parts.begin(), parts.end(), [&bd](const Part& x, const Part& y) {
+      if (x.cost != y.cost) return x.cost > y.cost;
+      const int32_t bx = bd[x.w.ob].b_tbase, by = bd[y.w.ob].b_tbase;
+      if (bx != by) return bx < by;
+      if (x.w.n0 != y.w.n0) return x.w.n0 < y.w.n0;
+      if (x.w.ob != y.w.ob) return x.w.ob < y.w.ob;
+      return x.w.m0 < y.w.m0;
+    });
+  else
+    std::stable_sort(parts.begin(), parts.end(), [](const Part& x, const Part& y) { return x.cost > y.cost; });
   p->work.clear();
   for (const Part& q : parts) p->work.push_back(q.w);
   if (p->work.size() > (size_t)INT32_MAX / 2) return fail(TAMM_ERR_UNSUPPORTED, "too many work items");
-  xcd_order(p->work, xcd_chunk());
+  xcd_order(p->work, p->xcd_chunk >= 0 ? p->xcd_chunk : xcd_chunk());
   p->config = config;
   p->k_splits = k_splits;
   p->stats.work_items = (int64_t)p->work.size();
   p->stats.kernel_config = config;
   p->stats.k_splits = k_splits;
+  p->stats.xcd_chunk = p->xcd_chunk >= 0 ? p->xcd_chunk : xcd_chunk();
+  p->stats.tile_order = p->tile_order;
   p->stats.gather_layout = gather_layout(p);
   p->lay = make_layout(p, 0);
   size_t off = p->lay.end;
@@ -710,6 +734,7 @@ static int bind_plan(tamm_plan* p, void* dev_ptr, size_t bytes) {
   p->ws_bound = true;
   p->screened = false;
   p->executed = false;
+  p->split_src_A = p->split_src_B = nullptr;  // the workspace holds no split yet
   return TAMM_OK;
 }
 
@@ -738,6 +763,24 @@ extern "C" int tamm_plan_set_config(tamm_plan* p, int32_t config, int32_t k_spli
   const int rc = configure_work(p, config, k_splits);
   if (rc != TAMM_OK) return rc;
   return ok();
+}
+
+extern "C" int tamm_plan_set_constant(tamm_plan* p, int32_t which, int32_t constant) {
+  if (!p || (which != 0 && which != 1)) return fail(TAMM_ERR_ARG, "null plan or operand not 0 or 1");
+  const bool is_a = (which == 0) != p->swapped;  // lhs is A unless it holds out's last label
+  (is_a ? p->const_A : p->const_B) = constant != 0;
+  (is_a ? p->split_src_A : p->split_src_B) = nullptr;  // split again at the next execution
+  return ok();
+}
+
+extern "C" int tamm_plan_set_order(tamm_plan* p, int32_t tile_order, int32_t chunk) {
+  if (!p) return fail(TAMM_ERR_ARG, "null plan");
+  if (tile_order != 0 && tile_order != 1) return fail(TAMM_ERR_ARG, "tile order must be 0 or 1");
+  if (chunk < -1 || chunk > (1 << 20)) return fail(TAMM_ERR_ARG, "chunk must be -1, 0 or a positive item count");
+  p->tile_order = tile_order;
+  p->xcd_chunk = chunk;
+  const int rc = configure_work(p, p->config, p->k_splits);
+  return rc == TAMM_OK ? ok() : rc;
 }
 
 extern "C" const char* tamm_config_name(int32_t precision, int32_t config) {
@@ -803,7 +846,9 @@ static int contract_launch(tamm_plan* p, double alpha, double beta, hipStream_t 
       pa.aligned = p->prec == TAMM_PREC_BF16X4_ALIGNED ? 1 : 0;
       pa.planes = p->planes ? 1 : 0;
       pa.plane_stride = p->A->numel;
-      HIP_TRY(launch_prep_split(pa, !p->a_kc, s));
+      // a constant operand keeps the split of an earlier execution from the same storage
+      if (!(p->const_A && p->split_src_A == p->A->dev)) HIP_TRY(launch_prep_split(pa, !p->a_kc, s));
+      p->split_src_A = p->const_A ? (const void*)p->A->dev : nullptr;
       PrepParams pbp = pa;
       pbp.x = p->B->dev;
       pbp.out = (uint64_t*)(p->ws + p->off_xB);
@@ -811,7 +856,8 @@ static int contract_launch(tamm_plan* p, double alpha, double beta, hipStream_t 
       pbp.n_items = p->prepB_items;
       pbp.n_blocks = (int32_t)p->prepB.size();
       pbp.plane_stride = p->B->numel;
-      HIP_TRY(launch_prep_split(pbp, !p->b_kc, s));
+      if (!(p->const_B && p->split_src_B == p->B->dev)) HIP_TRY(launch_prep_split(pbp, !p->b_kc, s));
+      p->split_src_B = p->const_B ? (const void*)p->B->dev : nullptr;
       cp.single.A = (const double*)(p->ws + p->off_xA);
       cp.single.B = (const double*)(p->ws + p->off_xB);
       if (p->planes) {
@@ -1094,43 +1140,65 @@ extern "C" int tamm_plan_autotune(tamm_plan* p, void* workspace, size_t bytes, v
   int rc = check_tensors(p);
   if (rc != TAMM_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
-  CacheEntry best{-1, 1, 0, 1e30};
-  if (!cache_lookup(cache_path, p->signature, "plan", best)) {
+  // cache entries of kind "plan2" hold the configuration, K splits and die chunk (grid field)
+  CacheEntry best{-1, 1, -1, 1e30};
+  if (!cache_lookup(cache_path, p->signature, "plan2", best)) {
     if (reps <= 0) reps = 3;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
+    // one candidate: configure, bind, warm up, fastest of reps (alpha = 0, beta = 1 leaves out
+    // unchanged for finite operands while doing the full work)
+    auto trial = [&](int c, int ks, float* ms) -> int {
+      *ms = 1e30f;
+      if (configure_work(p, c, ks) != TAMM_OK || p->ws_size > bytes) return TAMM_OK;
+      int r = bind_plan(p, workspace, bytes);
+      if (r != TAMM_OK) return r;
+      if ((r = tamm_plan_execute(p, 0.0, 1.0, stream)) != TAMM_OK) return r;
+      for (int i = 0; i < reps; ++i) {
+        HIP_TRY(hipEventRecord(e0, s));
+        if ((r = tamm_plan_execute(p, 0.0, 1.0, stream)) != TAMM_OK) return r;
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float one = 0;
+        HIP_TRY(hipEventElapsedTime(&one, e0, e1));
+        *ms = std::min(*ms, one);
+      }
+      return TAMM_OK;
+    };
+    const int chunk0 = p->xcd_chunk;
     const int64_t ntiles_max = tiles_for(p, 0).first;
-    for (int c = 0; c < cfg_count(p->prec); ++c) {
+    for (int c = 0; c < cfg_count(p->prec) && rc == TAMM_OK; ++c) {
       const int64_t nt = tiles_for(p, c).first;
       for (int ks : {1, 2, 4, 8}) {
         if (ks > 1 && nt * ks > 4 * std::max<int64_t>(ntiles_max, 2048)) continue;
-        if (configure_work(p, c, ks) != TAMM_OK || p->ws_size > bytes) continue;
-        if ((rc = bind_plan(p, workspace, bytes)) != TAMM_OK) break;
-        // alpha = 0, beta = 1 leaves out unchanged (for finite operands) while doing the full work;
-        // the fastest of `reps` timed executions counts (robust against clock and queue noise)
-        if ((rc = tamm_plan_execute(p, 0.0, 1.0, stream)) != TAMM_OK) break;
-        float ms = 1e30f;
-        for (int r = 0; r < reps && rc == TAMM_OK; ++r) {
-          HIP_TRY(hipEventRecord(e0, s));
-          rc = tamm_plan_execute(p, 0.0, 1.0, stream);
-          HIP_TRY(hipEventRecord(e1, s));
-          HIP_TRY(hipEventSynchronize(e1));
-          float one = 0;
-          HIP_TRY(hipEventElapsedTime(&one, e0, e1));
-          ms = std::min(ms, one);
-        }
-        if (rc != TAMM_OK) break;
-        if (ms < best.ms) best = CacheEntry{c, ks, 0, ms};
+        float ms = 0;
+        if ((rc = trial(c, ks, &ms)) != TAMM_OK) break;
+        if (ms < best.ms) best = CacheEntry{c, ks, chunk0, ms};
       }
-      if (rc != TAMM_OK) break;
+    }
+    // tile orders and die chunks for the fastest configuration (they change only the launch
+    // order); the cache's grid field holds chunk + order * 2^24
+    if (rc == TAMM_OK && best.config >= 0) {
+      best.grid = (chunk0 < 0 ? xcd_chunk() : chunk0) + (p->tile_order << 24);
+      const CacheEntry first = best;
+      for (int order : {0, 1})
+        for (int ch : {0, 16, 32, 64, 128}) {
+          p->xcd_chunk = ch;
+          p->tile_order = order;
+          float ms = 0;
+          if ((rc = trial(first.config, first.k_splits, &ms)) != TAMM_OK) break;
+          if (ms < best.ms) best = CacheEntry{first.config, first.k_splits, ch + (order << 24), ms};
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != TAMM_OK) return rc;
     if (best.config < 0) return fail(TAMM_ERR_WORKSPACE, "no configuration fits the %zu-byte workspace", bytes);
-    cache_store(cache_path, p->signature, "plan", best);
+    cache_store(cache_path, p->signature, "plan2", best);
   }
+  p->xcd_chunk = best.grid < 0 ? -1 : (best.grid & 0xFFFFFF);
+  p->tile_order = best.grid < 0 ? 0 : (best.grid >> 24) & 1;
   rc = configure_work(p, best.config, best.k_splits);
   if (rc != TAMM_OK) return rc;
   if (p->ws_size > bytes) return fail(TAMM_ERR_WORKSPACE, "cached configuration needs %zu bytes", p->ws_size);
@@ -1171,6 +1239,11 @@ struct tamm_group {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<double> g_alpha, g_beta;
+  // side streams (default priority) and events that run the layout classes' launches
+  // concurrently, forked after the screening launch and joined back into the caller's stream
+  hipStream_t side[kLayouts] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kLayouts] = {};
 };
 
 static void group_drop_graph(tamm_group* g) {
@@ -1518,11 +1591,39 @@ int group_enqueue(tamm_group* g, hipStream_t s) {
   sp.item_block = sp.item_prob + g->sitem_prob.size();
   sp.n_items = (int32_t)g->sitem_prob.size();
   HIP_TRY(launch_screen(sp, s));
-  // one persistent launch per gather layout present in the group
-  for (int c = 0; c < kLayouts; ++c) {
-    const int rc = group_enqueue_class(g, c, s);
-    if (rc != TAMM_OK) return rc;
+  // one persistent launch per gather layout present in the group.  With several, they run
+  // concurrently: the first on the caller's stream, the others on side streams that wait for the
+  // screening and that the caller's stream then waits for, so the workgroups of one class take
+  // the compute units the tail of another leaves free (each workgroup only pulls work items
+  // from its own class's counter, so no launch waits on another)
+  int present[kLayouts], np = 0;
+  for (int c = 0; c < kLayouts; ++c)
+    if (g->cls_begin[c + 1] > g->cls_begin[c]) present[np++] = c;
+  static const bool serial = [] {
+    const char* e = getenv("TAMM_GROUP_SERIAL");
+    return e && atoi(e) != 0;
+  }();
+  if (np <= 1 || serial) {
+    for (int i = 0; i < np; ++i) {
+      const int rc = group_enqueue_class(g, present[i], s);
+      if (rc != TAMM_OK) return rc;
+    }
+    return TAMM_OK;
   }
+  if (!g->ev_fork) HIP_TRY(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(g->ev_fork, s));
+  for (int i = 1; i < np; ++i) {
+    const int c = present[i];
+    if (!g->side[c]) HIP_TRY(hipStreamCreateWithFlags(&g->side[c], hipStreamNonBlocking));
+    if (!g->ev_join[c]) HIP_TRY(hipEventCreateWithFlags(&g->ev_join[c], hipEventDisableTiming));
+    HIP_TRY(hipStreamWaitEvent(g->side[c], g->ev_fork, 0));
+    const int rc = group_enqueue_class(g, c, g->side[c]);
+    if (rc != TAMM_OK) return rc;
+    HIP_TRY(hipEventRecord(g->ev_join[c], g->side[c]));
+  }
+  const int rc = group_enqueue_class(g, present[0], s);
+  if (rc != TAMM_OK) return rc;
+  for (int i = 1; i < np; ++i) HIP_TRY(hipStreamWaitEvent(s, g->ev_join[present[i]], 0));
   return TAMM_OK;
 }
 
@@ -1746,7 +1847,14 @@ extern "C" int tamm_group_stats(const tamm_group* g, int32_t* config, int32_t* g
 }
 
 extern "C" int tamm_group_destroy(tamm_group* g) {
-  if (g) group_drop_graph(g);
+  if (g) {
+    group_drop_graph(g);
+    for (int c = 0; c < kLayouts; ++c) {
+      if (g->side[c]) (void)hipStreamDestroy(g->side[c]);
+      if (g->ev_join[c]) (void)hipEventDestroy(g->ev_join[c]);
+    }
+    if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
+  }
   delete g;
   return ok();
 }

@@ -116,6 +116,7 @@ def test_autotune_plan_and_group(tmp_path):
     again = tm.Plan(m["O"], m["labels"][2], m["L"], m["labels"][5], m["R"], m["labels"][8])
     again.autotune(cache, reps=1)
     assert again.stats()["kernel_config"] == st["kernel_config"] and again.stats()["k_splits"] == st["k_splits"]
+    assert again.stats()["xcd_chunk"] == st["xcd_chunk"] and again.stats()["tile_order"] == st["tile_order"]
     group = tm.Group([x["plan"] for x in members])
     group.autotune(cache, reps=1)
     group.execute([x["alpha"] for x in members], [0.0] * len(members))
@@ -125,7 +126,9 @@ def test_autotune_plan_and_group(tmp_path):
         rel, _ = max_rel(x["O"].to_blocks(), oracle_blocks(x, tiles), keys=tiles)
         assert rel <= 1e-12
     lines = open(cache).read().strip().splitlines()
-    assert any(" plan " in ln for ln in lines)
+    # plan entries: configuration, K splits, die chunk + tile order * 2^24
+    assert any(" plan2 " in ln and int(ln.split()[4]) & 0xFFFFFF in (0, 16, 32, 64, 128) and int(ln.split()[4]) >> 24 in (0, 1)
+               for ln in lines)
     # one entry per gather layout class of the group
     assert sorted(ln.split()[1] for ln in lines if ln.split()[1].startswith("group")) == [f"group{c}" for c in range(8)]
     # members of more than one class, each class with its own launch and configuration

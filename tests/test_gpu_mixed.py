@@ -190,3 +190,31 @@ def test_full_size_sampled_blocks(full_size, precision, term):
     assert worst <= 1.0, (precision, term, "element-wise bound exceeded", worst)
     rel, mx = max_rel({t: got[t] for t in pick}, ref, pick)
     assert rel <= TOL[precision], (precision, term, rel, mx)
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16x4_aligned"])
+def test_constant_operand_split_is_reused(precision):
+    prob = Problem(16, 48, 8, 16)
+    V = prob.gpu_tensor("V_vvvv", "vvvv")
+    T = prob.gpu_tensor("T2", "vvoo")
+    R1, R2 = prob.gpu_tensor(None, "vvoo", fill=False), prob.gpu_tensor(None, "vvoo", fill=False)
+    plain = tm.Plan(R1, "abij", V, "abcd", T, "cdij", precision=precision)
+    plain.execute(0.5, 0.0)
+    const = tm.Plan(R2, "abij", V, "abcd", T, "cdij", precision=precision)
+    const.set_constant(0)
+    const.execute(0.5, 0.0)  # splits V
+    const.execute(0.5, 0.0)  # reuses the split
+    torch.cuda.synchronize()
+    assert torch.equal(R1.data, R2.data)
+    # the split is reused until the operand is declared again: values changed behind the plan's
+    # back do not reach the result ...
+    old = R2.data.clone()
+    V.data.mul_(2.0)
+    const.execute(0.5, 0.0)
+    torch.cuda.synchronize()
+    assert torch.equal(R2.data, old)
+    # ... and after declaring it again they do (exact: the split of 2x is twice the split of x)
+    const.set_constant(0)
+    const.execute(0.5, 0.0)
+    torch.cuda.synchronize()
+    assert torch.equal(R2.data[:R2.numel], 2.0 * old[:R2.numel])
