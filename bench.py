@@ -48,25 +48,26 @@ def log(*a):
 
 
 def kernel_source_digest() -> str:
-    """sha256 over the library's HIP/C++ sources and public header: identifies the kernels that a
-    stored counter measurement was taken on."""
+    """sha256 over the sources that fix the float64 contraction kernel and its work decomposition
+    (the kernels, their device helpers and shared layouts, the planner): identifies the kernels that
+    a stored counter measurement was taken on."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2201_01257_amd", "csrc")
-    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".h", ".cpp")))
-    for f in files + [os.path.join(ROOT, "include", "tamm_mi.h")]:
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for name in ("kernels.hip", "device_util.h", "internal.h", "plan.cpp"):
+        h.update(name.encode())
+        with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, config_name: str, work_items: int, record: str = TRAFFIC_RECORD):
+def measured_traffic(workload: str, config_name: str, work_items: int, record: str = TRAFFIC_RECORD,
+                     xcd_chunk=None, tile_order=None):
     """HBM bytes per launch of the measured contraction (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
     from a committed counter record (the ladder's by default), if it was taken on these kernel
-    sources with the same workload, configuration and work decomposition (a record keeps one entry
-    per measured configuration and K split); otherwise None."""
+    sources with the same workload, configuration, work decomposition and launch order (a record
+    keeps one entry per measured configuration and K split); otherwise None."""
     try:
         with open(record) as fh:
             rec = json.load(fh)
@@ -75,8 +76,13 @@ def measured_traffic(workload: str, config_name: str, work_items: int, record: s
     if rec.get("source_sha256") != kernel_source_digest() or rec.get("workload") != workload:
         return None
     for e in rec.get("entries", []):
-        if e.get("config") == config_name and e.get("work_items") == work_items:
-            return int(e["hbm_bytes_per_launch"])
+        if e.get("config") != config_name or e.get("work_items") != work_items:
+            continue
+        if xcd_chunk is not None and e.get("xcd_chunk", xcd_chunk) != xcd_chunk:
+            continue
+        if tile_order is not None and e.get("tile_order", tile_order) != tile_order:
+            continue
+        return int(e["hbm_bytes_per_launch"])
     return None
 
 
@@ -272,7 +278,9 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_F64_MFMA_TFLOPS, 4),
                 "traffic": measured_traffic(args.workload, plans["ladder"].config_name(),
-                                            plans["ladder"].stats()["work_items"]),
+                                            plans["ladder"].stats()["work_items"],
+                                            xcd_chunk=plans["ladder"].stats()["xcd_chunk"],
+                                            tile_order=plans["ladder"].stats()["tile_order"]),
                 "kernel": "k_contract_f64 (ladder, " + plans["ladder"].config_name() + ")",
                 "kernel_ms": round(lad_ms, 4)}
 

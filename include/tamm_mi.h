@@ -313,8 +313,8 @@ int tamm_contract_cache_clear(void);
 
 /* For callers that cannot allocate device memory (code under graph capture, tight serving loops,
  * harnesses that forbid hipMalloc): tamm_contract with no workspace argument.  The workspace is a
- * file-scope device array of the library, tamm_contract_noalloc_max_workspace() bytes (64 MiB) on
- * each GPU the library runs on, held until the process ends; the call allocates nothing (no
+ * file-scope device array of the library, TAMM_NOALLOC_WORKSPACE_BYTES (64 MiB) on each GPU the
+ * library runs on, held until the process ends; the call allocates nothing (no
  * hipMalloc, no library allocation).  Same operation, arguments, plan cache and results as
  * tamm_contract on the current device; the stream must belong to that device.  ERR_WORKSPACE,
  * before anything is enqueued, when the contraction needs more workspace than the array holds
@@ -325,7 +325,7 @@ int tamm_contract_cache_clear(void);
 int tamm_contract_noalloc(tamm_tensor* out, const char* out_lbl, const tamm_tensor* lhs, const char* lhs_lbl,
                           const tamm_tensor* rhs, const char* rhs_lbl, int32_t precision, double alpha, double beta,
                           void* stream);
-size_t tamm_contract_noalloc_max_workspace(void);
+#define TAMM_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
 
 /* ------------------------------------------------------------------------------------------
  * Groups: many independent plans executed together (the single-GPU analogue of running the

@@ -72,7 +72,6 @@ SIGNATURES = {
     "tamm_contract_cache_count": (c_int, [P(c_i64)]),
     "tamm_contract_cache_clear": (c_int, []),
     "tamm_contract_noalloc": (c_int, [c_vp, c_char_p, c_vp, c_char_p, c_vp, c_char_p, c_i32, c_dbl, c_dbl, c_vp]),
-    "tamm_contract_noalloc_max_workspace": (c_size_t, []),
     "tamm_group_create": (c_int, [P(c_vp), c_i32, P(c_vp)]),
     "tamm_group_workspace_size": (c_int, [c_vp, P(c_size_t)]),
     "tamm_group_bind_workspace": (c_int, [c_vp, c_vp, c_size_t]),
@@ -118,6 +117,8 @@ SIGNATURES = {
     "tamm_chol_ladder_strip_plans": (c_int, [c_vp, c_i32, P(c_vp), P(c_vp)]),
     "tamm_chol_ladder_destroy": (c_int, [c_vp]),
 }
+
+NOALLOC_WORKSPACE_BYTES = 64 << 20  # TAMM_NOALLOC_WORKSPACE_BYTES of the header
 
 STATUS = {
     0: "TAMM_OK",

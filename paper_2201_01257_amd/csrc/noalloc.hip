@@ -19,7 +19,7 @@ using namespace tamm;
 
 namespace {
 
-constexpr size_t kScratchBytes = size_t(64) << 20;  // 64 MiB per GPU
+constexpr size_t kScratchBytes = TAMM_NOALLOC_WORKSPACE_BYTES;  // 64 MiB per GPU
 constexpr int kMaxDevices = 64;
 
 std::mutex g_scratch_mu;
@@ -28,8 +28,6 @@ void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` on each device
 }  // namespace
 
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
-
-extern "C" size_t tamm_contract_noalloc_max_workspace(void) { return kScratchBytes; }
 
 extern "C" int tamm_contract_noalloc(tamm_tensor* out, const char* out_lbl, const tamm_tensor* lhs, const char* lhs_lbl,
                                      const tamm_tensor* rhs, const char* rhs_lbl, int32_t precision, double alpha,

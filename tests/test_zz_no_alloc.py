@@ -41,7 +41,15 @@ def test_noalloc_rejects_a_workspace_beyond_the_scratch_array():
     k = tm.Space.fixed(2048, 1)
     C, A, B = tm.Tensor([m, m], device=None), tm.Tensor([m, k], device=None), tm.Tensor([k, m], device=None)
     need = tm.Plan(C, "ij", A, "ik", B, "kj", bind=False).workspace_size()
-    assert need > _lib.load().tamm_contract_noalloc_max_workspace()
+    assert need > _lib.NOALLOC_WORKSPACE_BYTES
     with pytest.raises(tm.TammError) as e:
         tm.contract_noalloc(C, "ij", A, "ik", B, "kj", 1.0, 0.0, stream=None if torch.cuda.is_available() else 0)
     assert e.value.status == "TAMM_ERR_WORKSPACE"
+
+
+def test_header_constant_matches_binding():
+    import re
+
+    text = open(_lib.HEADER).read()
+    m = re.search(r"#define TAMM_NOALLOC_WORKSPACE_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.NOALLOC_WORKSPACE_BYTES
