@@ -147,3 +147,25 @@ def test_group_rejects_dependent_members():
     with pytest.raises(tm.TammError) as e:
         grp.execute([1.0, 0.25], [0.0, 1.0])
     assert e.value.status == "TAMM_ERR_ARG"
+
+
+@pytest.mark.slow
+def test_all_256_problems_graph_replay_sampled_blocks():
+    # the whole batched workload as one group (autotuned per layout class, captured, replayed
+    # twice with eager work between), one seeded output block of every problem checked
+    members = [build_member(d) for d in synth.batched_problems()]
+    assert len(members) == 256
+    group = tm.Group([m["plan"] for m in members])
+    group.autotune("", reps=1)
+    alphas = [m["alpha"] for m in members]
+    group.capture(alphas, [0.0] * len(members))
+    for rep in range(2):
+        for m in members:
+            m["O"].data.fill_(float("nan"))  # beta = 0 never reads out
+        group.execute(alphas, [0.0] * len(members))
+        torch.cuda.synchronize()
+    rng = np.random.default_rng(256)
+    for i, m in enumerate(members):
+        tiles = sample_tiles(m, rng, k=1)
+        rel, mx = max_rel(m["O"].to_blocks(), oracle_blocks(m, tiles), keys=tiles)
+        assert rel <= 1e-12, (i, m["desc"], rel, mx)
