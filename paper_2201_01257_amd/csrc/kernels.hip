@@ -149,6 +149,18 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int j = 0; j < FN; ++j) acc[i][j] = (d4_t){0.0, 0.0, 0.0, 0.0};
 
+    // A tile that runs past its block holds fewer live 16 x 16 output fragments than waves x
+    // fragments per wave.  When dealing the live ones round-robin over the waves (fragment f to
+    // wave f % NW, slot f / NW) shortens the longest wave's share, each wave multiplies only its
+    // dealt fragments: the workgroup's barrier-to-barrier time is set by that longest share.
+    // Every output element is still summed by one wave in the same k order, so the results are
+    // the same bits either way.
+    constexpr int NW = WGM * WGN, NSLOT = FM * FN;
+    const int fml = min(MT / 16, (blk.mext - w.m0 + 15) >> 4), fnl = min(NT / 16, (blk.next - w.n0 + 15) >> 4);
+    const bool dealt = (fml * fnl + NW - 1) / NW < NSLOT;
+    const int wv = wave_uniform(wave);
+    const int nslot = dealt ? max(0, min(NSLOT, (fml * fnl - wv + NW - 1) / NW)) : NSLOT;
+
     if (pb < pe) {
       auto store = [&](int b) {
 #pragma unroll
@@ -184,11 +196,73 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
         __builtin_amdgcn_s_setprio(0);
         post();
       };
-      chunk_pipeline<KT, 0>(g, pairs, pb, pe, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next, store, compute);
+      if (!dealt) {
+        chunk_pipeline<KT, 0>(g, pairs, pb, pe, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next, store, compute);
+      } else {
+        // LDS offsets of this wave's dealt fragments: the fragment's first row (the same for the
+        // whole wave) plus the lane's own row and k-step position
+        const int lane_off = lr * LD + lq;
+        int sa[NSLOT], sb[NSLOT];
+#pragma unroll
+        for (int q = 0; q < NSLOT; ++q) {
+          const int f = wv + q * NW, fi = f / fnl, fj = f - fi * fnl;
+          sa[q] = wave_uniform(fi * 16 * LD);
+          sb[q] = wave_uniform(fj * 16 * LD);
+        }
+        auto compute_dealt = [&](int b, bool, auto&& stage, auto&& post) {
+          const double* as = As[b] + lane_off;
+          const double* bs = Bs[b] + lane_off;
+          __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+#pragma unroll
+            for (int q = 0; q < NSLOT; ++q)
+              if (q < nslot)
+                acc[q / FN][q % FN] =
+                    __builtin_amdgcn_mfma_f64_16x16x4f64(as[sa[q] + 4 * s], bs[sb[q] + 4 * s], acc[q / FN][q % FN], 0, 0, 0);
+            if (s == 0) stage();
+          }
+          __builtin_amdgcn_s_setprio(0);
+          post();
+        };
+        chunk_pipeline<KT, 0>(g, pairs, pb, pe, pool, pr.A, pr.B, w.m0, w.n0, blk.mext, blk.next, store, compute_dealt);
+      }
     }
 
     // epilogue: lane holds D[m][n] for m = 4r + lane/16 (register r), n = lane%16
-    if (nsplit > 1) {
+    if (dealt) {
+      // per dealt fragment: its rows and columns, then the same writes as below
+      const double alpha = pr.alpha, beta = pr.beta;
+      __attribute__((address_space(1))) double* __restrict__ Cg = (__attribute__((address_space(1))) double*)pr.C;
+#pragma unroll
+      for (int q = 0; q < NSLOT; ++q) {
+        if (q >= nslot) continue;
+        const int f = wv + q * NW, fi = f / fnl, fj = f - fi * fnl;
+        const int n = fj * 16 + lr;
+        if (nsplit > 1) {
+          double* part = pr.partial + ((int64_t)w.tile + split) * (MT * NT);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) part[(fi * 16 + 4 * r + lq) * NT + n] = acc[q / FN][q % FN][r];
+        } else {
+          const int ct = gload(pool + blk.c_tabN + w.n0 + n);
+          int32_t rt[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) rt[r] = gload(pool + blk.c_tabM + w.m0 + fi * 16 + 4 * r + lq);
+          double old[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const bool live = w.m0 + fi * 16 + 4 * r + lq < blk.mext && w.n0 + n < blk.next;
+            old[r] = (beta != 0.0 && live) ? Cg[blk.c_off + rt[r] + ct] : 0.0;
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const bool live = w.m0 + fi * 16 + 4 * r + lq < blk.mext && w.n0 + n < blk.next;
+            const double v = alpha * acc[q / FN][q % FN][r];
+            if (live) Cg[blk.c_off + rt[r] + ct] = (beta == 0.0) ? v : beta * old[r] + v;
+          }
+        }
+      }
+    } else if (nsplit > 1) {
       double* part = pr.partial + ((int64_t)w.tile + split) * (MT * NT);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
