@@ -1168,28 +1168,33 @@ extern "C" int tamm_plan_autotune(tamm_plan* p, void* workspace, size_t bytes, v
     };
     const int chunk0 = p->xcd_chunk;
     const int64_t ntiles_max = tiles_for(p, 0).first;
+    std::vector<CacheEntry> ranked;  // every (configuration, K splits) at the current launch order
     for (int c = 0; c < cfg_count(p->prec) && rc == TAMM_OK; ++c) {
       const int64_t nt = tiles_for(p, c).first;
       for (int ks : {1, 2, 4, 8}) {
         if (ks > 1 && nt * ks > 4 * std::max<int64_t>(ntiles_max, 2048)) continue;
         float ms = 0;
         if ((rc = trial(c, ks, &ms)) != TAMM_OK) break;
+        if (ms < 1e29f) ranked.push_back(CacheEntry{c, ks, chunk0, ms});
         if (ms < best.ms) best = CacheEntry{c, ks, chunk0, ms};
       }
     }
-    // tile orders and die chunks for the fastest configuration (they change only the launch
-    // order); the cache's grid field holds chunk + order * 2^24
+    // tile orders and die chunks (they change only the launch order) for the three fastest
+    // (configuration, K splits) of the first pass, since a configuration that loses at one order
+    // can win at another; the cache's grid field holds chunk + order * 2^24
     if (rc == TAMM_OK && best.config >= 0) {
       best.grid = (chunk0 < 0 ? xcd_chunk() : chunk0) + (p->tile_order << 24);
-      const CacheEntry first = best;
-      for (int order : {0, 1})
-        for (int ch : {0, 16, 32, 64, 128}) {
-          p->xcd_chunk = ch;
-          p->tile_order = order;
-          float ms = 0;
-          if ((rc = trial(first.config, first.k_splits, &ms)) != TAMM_OK) break;
-          if (ms < best.ms) best = CacheEntry{first.config, first.k_splits, ch + (order << 24), ms};
-        }
+      std::stable_sort(ranked.begin(), ranked.end(), [](const CacheEntry& x, const CacheEntry& y) { return x.ms < y.ms; });
+      if (ranked.size() > 3) ranked.resize(3);
+      for (const CacheEntry& cand : ranked)
+        for (int order : {0, 1})
+          for (int ch : {0, 16, 32, 64, 128}) {
+            p->xcd_chunk = ch;
+            p->tile_order = order;
+            float ms = 0;
+            if ((rc = trial(cand.config, cand.k_splits, &ms)) != TAMM_OK) break;
+            if (ms < best.ms) best = CacheEntry{cand.config, cand.k_splits, ch + (order << 24), ms};
+          }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
