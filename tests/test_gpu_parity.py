@@ -173,6 +173,31 @@ def test_bitwise_reproducible_and_order_independent():
     assert torch.equal(outs[0], outs[1]) and torch.equal(outs[1], outs[2])
 
 
+@pytest.mark.parametrize("shape", [SMALL, ODD], ids=["pairs", "single"])
+@pytest.mark.parametrize("term", ["ladder", "ring", "hh_int", "t1_o"])
+def test_every_config_gives_the_same_bits_without_k_splits(term, shape):
+    """Without K splits every tile shape sums each output element in the same order (k-steps of
+    four in k order, chunk after chunk, pair after pair; padding adds exact zeros), and the edge
+    tiles that deal their fragments over the waves run the same products: all configurations
+    must write the same bits."""
+    prob = Problem(*shape)
+    (on, op, ol), (ln, lp, ll), (rn, rp, rl), a = TERMS[term]
+    L = prob.gpu_tensor(ln, lp)
+    R = prob.gpu_tensor(rn, rp)
+    O = prob.gpu_tensor(on, op)
+    plan = tm.Plan(O, ol, L, ll, R, rl)
+    first = None
+    for c in range(plan.config_count()):
+        O.data.copy_(torch.linspace(-1.0, 1.0, O.data.numel(), dtype=torch.float64, device=O.data.device))
+        plan.set_config(c, 1)
+        plan.execute(-0.7, 0.3)
+        torch.cuda.synchronize()
+        if first is None:
+            first = O.data.clone()
+        else:
+            assert torch.equal(O.data, first), (term, plan.config_name(c))
+
+
 def test_denominator_bitwise():
     prob = Problem(*SMALL)
     R = prob.gpu_tensor("R", "vvoo")
