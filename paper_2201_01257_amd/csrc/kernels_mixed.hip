@@ -410,8 +410,13 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_f32(ContractParams 
 // past the rows or the K extent read zeros (offset beyond the buffer resource).
 // Same interface as Gather, for chunk_pipeline.
 // ---------------------------------------------------------------------------------------------
-// 16-byte unit permutation of LDS row r in the planes layout (rows of four 16-byte units).
-__device__ __forceinline__ int lds_swizzle(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+// LDS layout of a chunk in the planes layout: per plane, the 16-byte units (8 k of one row) are
+// stored k-group major, unit (k-group q, row r) at q*ROWS + (r ^ 2q).  An MFMA operand read (16
+// rows, one k-group per 16 lanes) is then a permutation of one aligned 256-byte block per 16
+// lanes, which the LDS serves without bank conflicts; the gather's stores (4 lanes per row, one
+// k-group each) put every 8 consecutive lanes on 8 distinct 16-byte bank groups.
+template <int ROWS>
+__device__ __forceinline__ int lds_unit(int r, int q) { return q * ROWS + (r ^ (2 * q)); }
 
 template <int MT, int NT, int KT, int NTHR, int NS>
 struct PlaneGather {
@@ -476,9 +481,9 @@ struct PlaneGather {
 };
 
 // ---------------------------------------------------------------------------------------------
-// split bfloat16 products (v_mfma_f32_16x16x32_bf16).  LDS holds NS slice planes per operand as
-// [row][k] bfloat16 with a row stride of KT+8 elements (an odd number of 16-byte units, so the
-// 16-byte fragment reads of 16 consecutive rows hit distinct banks).
+// split bfloat16 products (v_mfma_f32_16x16x32_bf16).  LDS holds NS slice planes per operand: in
+// the planes layout as 16-byte units placed by lds_unit; in the packed layout as [row][k] bfloat16
+// with a row stride of KT+8 elements (an odd number of 16-byte units).
 // ---------------------------------------------------------------------------------------------
 template <int MT, int NT, int KT, int WGM, int WGN, bool ALIGNED, bool A_KC, bool B_KC, bool PLANES>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParams P) {
@@ -486,9 +491,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
   constexpr int WM = MT / WGM, WN = NT / WGN, FM = WM / 16, FN = WN / 16;
   constexpr int NS = ALIGNED ? 4 : 3;
   // LDS rows of KT bfloat16.  Packed layout: padded to an odd number of 16-byte units.  Planes
-  // layout: unpadded, the 16-byte unit u of row r stored at unit u ^ lds_swizzle(r), which keeps
-  // the 16-byte stores (4 rows x 4 units per 16 lanes) and the MFMA operand reads (16 rows, one
-  // unit) free of bank conflicts for 32 or 64 banks.
+  // layout: a plane of MT (NT) rows x KT holds MT*KT elements, unit (q, r) at lds_unit.
   constexpr int LD = PLANES ? KT : KT + 8;
   static_assert(KT % 32 == 0 && kSplitWindow % KT == 0, "chunks of whole MFMA k-steps tile the window");
   static_assert(PLANES ? KT == 32 : ((LD * 2) / 16) % 2 == 1, "LDS row layout");
@@ -503,12 +506,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
     const int r = wm * WM + i * 16 + lr;
-    a_frag[i] = r * LD + 8 * (PLANES ? (lq ^ lds_swizzle(r)) : lq);
+    a_frag[i] = PLANES ? 8 * lds_unit<MT>(r, lq) : r * LD + 8 * lq;
   }
 #pragma unroll
   for (int j = 0; j < FN; ++j) {
     const int r = wn * WN + j * 16 + lr;
-    b_frag[j] = r * LD + 8 * (PLANES ? (lq ^ lds_swizzle(r)) : lq);
+    b_frag[j] = PLANES ? 8 * lds_unit<NT>(r, lq) : r * LD + 8 * lq;
   }
   const int item = blockIdx.x;
   if (item >= P.n_work) return;
@@ -543,14 +546,12 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_contract_bf16s(ContractParam
 #pragma unroll
           for (int j = 0; j < G::AJ; ++j) {
             if (!G::a_live(tid + j * NTHR)) continue;
-            const int r = g.lds_row(j);
-            *reinterpret_cast<u4_t*>(&As[b][s * MT * LD + r * LD + 8 * ((g.lds_k(j) / 8) ^ lds_swizzle(r))]) = g.ra[s][j];
+            *reinterpret_cast<u4_t*>(&As[b][s * MT * LD + 8 * lds_unit<MT>(g.lds_row(j), g.lds_k(j) / 8)]) = g.ra[s][j];
           }
 #pragma unroll
           for (int j = 0; j < G::BJ; ++j) {
             if (!G::b_live(tid + j * NTHR)) continue;
-            const int r = g.lds_row(j);
-            *reinterpret_cast<u4_t*>(&Bs[b][s * NT * LD + r * LD + 8 * ((g.lds_k(j) / 8) ^ lds_swizzle(r))]) = g.rb[s][j];
+            *reinterpret_cast<u4_t*>(&Bs[b][s * NT * LD + 8 * lds_unit<NT>(g.lds_row(j), g.lds_k(j) / 8)]) = g.rb[s][j];
           }
         }
       } else {  // one packed element: its NS slices to NS planes
