@@ -109,25 +109,68 @@ hipError_t launch_screen(const ScreenParams& p, hipStream_t s) {
 // from a counter (the grouped launch); the item order is the plan's.  The operands' gather
 // layouts (A_KC, B_KC) are template parameters: "layout" = 2*A_KC + B_KC.
 // ---------------------------------------------------------------------------------------------
+// LDS layout of one operand chunk (ROWS rows x KT summed indices, float64), chosen by the LDS's
+// measured service pattern on gfx950 (8-byte reads: 32 lanes per cycle over 64 four-byte banks;
+// 8-byte writes: 16 lanes per cycle over 32 banks; 16-byte writes: 8 lanes per cycle over 32
+// banks) for the MFMA operand reads (8 bytes per lane: lanes 16q + r read row R0 + r at k-step
+// position q) and the gather's stores:
+//   kind 0, an operand whose stride-1 label is summed (lanes gather along k), up to 128 rows:
+//     [row][k] with a row stride of KT + 2 doubles -- half the stride is odd, so the 16 rows x 2 k
+//     of a read cycle land on 32 distinct 8-byte bank pairs, and a lane's two adjacent k go in
+//     one aligned 16-byte store;
+//   kind 1, the other operands with rows = 16 mod 32 or at least 128 rows: [k][row] with a k
+//     stride of rows + pad (16 mod 32 doubles) -- 16 consecutive rows of one k fill half the
+//     banks and the next k the other half, and a lane's two adjacent rows go in one store;
+//   kind 2, otherwise (where that padding would cost LDS occupancy): [row][k] with an odd row
+//     stride KT + 1, reads two-way conflicted.
+template <int ROWS, int KT, bool KC>
+struct LdsLayout {
+  static constexpr int KIND = KC ? (ROWS <= 128 ? 0 : 2) : ((ROWS % 32 == 16 || ROWS >= 128) ? 1 : 2);
+  static constexpr int LDR = ROWS + ((48 - ROWS % 32) % 32);  // kind 1: k stride, 16 mod 32
+  static constexpr int RS = KIND == 1 ? 1 : (KIND == 0 ? KT + 2 : KT + 1);  // element stride between rows
+  static constexpr int KS = KIND == 1 ? LDR : 1;                            // ... between k positions
+  static constexpr int SIZE = KIND == 1 ? KT * LDR : ROWS * RS;             // doubles per buffer
+  static constexpr int PAIR = KC ? KS : RS;  // distance of the two elements of a 16-byte gather load
+  static constexpr bool STORE16 = PAIR == 1 && (KC ? RS : KS) % 2 == 0;  // they go in one aligned store
+  static_assert(KIND != 1 || LDR % 32 == 16, "kind 1 stride");
+  static_assert(KIND != 0 || (RS / 2) % 2 == 1, "kind 0 stride");
+  static_assert(SIZE % 2 == 0, "16-byte aligned buffers");
+  __device__ static constexpr int at(int row, int k) { return row * RS + k * KS; }
+};
+
+// A gather load's VEC elements into LDS: one 16-byte store when they are adjacent and aligned,
+// else one store each, PAIR elements apart
+template <int VEC, int PAIR, bool STORE16>
+__device__ __forceinline__ void lds_store(double* dst, const double* v) {
+  if constexpr (VEC == 2 && STORE16) {
+    typedef double d2_t __attribute__((ext_vector_type(2)));
+    *reinterpret_cast<d2_t*>(dst) = (d2_t){v[0], v[1]};
+  } else {
+    dst[0] = v[0];
+    if constexpr (VEC == 2) dst[PAIR] = v[1];
+  }
+}
+
 template <int MT, int NT, int KT, int WGM, int WGN, int OCC, bool A_KC, bool B_KC, int VEC>
 __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(OCC))) void k_contract_f64(ContractParams P) {
   constexpr int NTHR = 64 * WGM * WGN;
   constexpr int WM = MT / WGM, WN = NT / WGN;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int LD = KT + 1;  // LDS row stride in doubles (odd: conflict-free)
   constexpr int NS = KT / 4;  // MFMA k-steps per chunk
   static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile must be a multiple of 16");
   static_assert(KT % 4 == 0 && NS >= 2, "KT a multiple of 4, at least 8");
   using G = Gather<MT, NT, KT, NTHR, A_KC, B_KC, double, VEC>;
-  __shared__ double As[2][MT * LD];
-  __shared__ double Bs[2][NT * LD];
+  using LA = LdsLayout<MT, KT, A_KC>;
+  using LB = LdsLayout<NT, KT, B_KC>;
+  __shared__ __attribute__((aligned(16))) double As[2][LA::SIZE];
+  __shared__ __attribute__((aligned(16))) double Bs[2][LB::SIZE];
   __shared__ int s_next;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
   const int lr = lane & 15, lq = lane >> 4;
-  const int a_frag = (wm * WM + lr) * LD + lq;  // this lane's operand reads at k-step 0
-  const int b_frag = (wn * WN + lr) * LD + lq;
+  const int a_frag = LA::at(wm * WM + lr, lq);  // this lane's operand reads at k-step 0
+  const int b_frag = LB::at(wn * WN + lr, lq);
   G g;
   g.init(tid);
 
@@ -164,27 +207,29 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
     if (pb < pe) {
       auto store = [&](int b) {
 #pragma unroll
-        for (int e = 0; e < G::AE; ++e) As[b][g.a_lds_row(e) * LD + g.a_lds_k(e)] = g.ra[e];
+        for (int e = 0; e < G::AE; e += VEC)
+          lds_store<VEC, LA::PAIR, LA::STORE16>(&As[b][LA::at(g.a_lds_row(e), g.a_lds_k(e))], &g.ra[e]);
 #pragma unroll
-        for (int e = 0; e < G::BE; ++e) Bs[b][g.b_lds_row(e) * LD + g.b_lds_k(e)] = g.rb[e];
+        for (int e = 0; e < G::BE; e += VEC)
+          lds_store<VEC, LB::PAIR, LB::STORE16>(&Bs[b][LB::at(g.b_lds_row(e), g.b_lds_k(e))], &g.rb[e]);
       };
       auto compute = [&](int b, bool, auto&& stage, auto&& post) {
         const double* as = As[b] + a_frag;
         const double* bs = Bs[b] + b_frag;
         double af[2][FM], bf[2][FN];
 #pragma unroll
-        for (int i = 0; i < FM; ++i) af[0][i] = as[i * 16 * LD];
+        for (int i = 0; i < FM; ++i) af[0][i] = as[i * 16 * LA::RS];
 #pragma unroll
-        for (int j = 0; j < FN; ++j) bf[0][j] = bs[j * 16 * LD];
+        for (int j = 0; j < FN; ++j) bf[0][j] = bs[j * 16 * LB::RS];
         __builtin_amdgcn_s_setprio(1);  // MFMA phase first when waves of two workgroups compete
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
           const int cur = s & 1, nxt = cur ^ 1;
           if (s + 1 < NS) {  // operands of the next k-step while this step's MFMAs run
 #pragma unroll
-            for (int i = 0; i < FM; ++i) af[nxt][i] = as[i * 16 * LD + 4 * (s + 1)];
+            for (int i = 0; i < FM; ++i) af[nxt][i] = as[i * 16 * LA::RS + 4 * (s + 1) * LA::KS];
 #pragma unroll
-            for (int j = 0; j < FN; ++j) bf[nxt][j] = bs[j * 16 * LD + 4 * (s + 1)];
+            for (int j = 0; j < FN; ++j) bf[nxt][j] = bs[j * 16 * LB::RS + 4 * (s + 1) * LB::KS];
           }
 #pragma unroll
           for (int i = 0; i < FM; ++i)
@@ -201,17 +246,16 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
       } else {
         // LDS offsets of this wave's dealt fragments: the fragment's first row (the same for the
         // whole wave) plus the lane's own row and k-step position
-        const int lane_off = lr * LD + lq;
         int sa[NSLOT], sb[NSLOT];
 #pragma unroll
         for (int q = 0; q < NSLOT; ++q) {
           const int f = wv + q * NW, fi = f / fnl, fj = f - fi * fnl;
-          sa[q] = wave_uniform(fi * 16 * LD);
-          sb[q] = wave_uniform(fj * 16 * LD);
+          sa[q] = wave_uniform(fi * 16 * LA::RS);
+          sb[q] = wave_uniform(fj * 16 * LB::RS);
         }
         auto compute_dealt = [&](int b, bool, auto&& stage, auto&& post) {
-          const double* as = As[b] + lane_off;
-          const double* bs = Bs[b] + lane_off;
+          const double* as = As[b] + LA::at(lr, lq);
+          const double* bs = Bs[b] + LB::at(lr, lq);
           __builtin_amdgcn_s_setprio(1);
 #pragma unroll
           for (int s = 0; s < NS; ++s) {
@@ -219,7 +263,8 @@ __global__ __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(
             for (int q = 0; q < NSLOT; ++q)
               if (q < nslot)
                 acc[q / FN][q % FN] =
-                    __builtin_amdgcn_mfma_f64_16x16x4f64(as[sa[q] + 4 * s], bs[sb[q] + 4 * s], acc[q / FN][q % FN], 0, 0, 0);
+                    __builtin_amdgcn_mfma_f64_16x16x4f64(as[sa[q] + 4 * s * LA::KS], bs[sb[q] + 4 * s * LB::KS],
+                                                         acc[q / FN][q % FN], 0, 0, 0);
             if (s == 0) stage();
           }
           __builtin_amdgcn_s_setprio(0);
