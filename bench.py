@@ -21,6 +21,7 @@ ladder contraction) and the oracle's CPU throughput on a bounded sample are repo
 from __future__ import annotations
 
 import argparse
+import atexit
 import gc
 import json
 import os
@@ -101,6 +102,7 @@ def resolve_tune_cache(args) -> str:
             fd, path = tempfile.mkstemp(prefix="tamm_tune_", suffix=".txt")
             os.close(fd)
             shutil.copyfile(TUNING_TABLE, path)
+            atexit.register(lambda p=path: os.path.exists(p) and os.unlink(p))
             args.tune_cache = path
             return "tuning table " + os.path.relpath(TUNING_TABLE, ROOT)
         args.tune_cache = ""
