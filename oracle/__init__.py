@@ -28,8 +28,10 @@ Pins: every function here is checked by the ``-m "not gpu"`` tests against somet
 than itself (dense brute force, a BLAS GEMM special case, the Eq. (cc9)-(cc11) identity,
 closed-form block counts, the worked tiling example of Fig. 1, invariants, finite
 differences).  The operand splits of the mixed-precision paths (``oracle.split``) are pinned
-by their own tests; the error of their float32 accumulation has no exact pin (parity unpinned
-beyond the tolerance each precision states).
+by their own tests.  The mixed-precision contractions themselves are checked against this
+float64 oracle element by element within a worst-case bound derived from the split definitions
+and the rounding of the matrix-core instructions, which is measured on the device on inputs
+whose exact sums are known (``tests/mixed_bound.py``, ``tests/test_gpu_mfma_rounding.py``).
 """
 
 from .tiling import Space, spin_conserving
