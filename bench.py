@@ -53,18 +53,48 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_digest() -> str:
-    """sha256 over the sources that fix the float64 contraction kernel and its work decomposition
-    (the kernels, their device helpers and shared layouts, the planner): identifies the kernels that
-    a stored counter measurement was taken on."""
+def _code_only(text: str) -> str:
+    """C/C++ source without comments and whitespace runs (string literals kept as they are)."""
+    import re
+
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == '"':  # string literal
+            j = i + 1
+            while j < n and text[j] != '"':
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return re.sub(r"\s+", " ", "".join(out)).strip()
+
+
+def kernel_source_digest(texts=None) -> str:
+    """sha256 over the code (comments and whitespace ignored) of the sources that fix the float64
+    contraction kernel and its work decomposition (the kernels, their device helpers and shared
+    layouts, the planner): identifies the kernels that a stored counter measurement was taken on.
+    `texts` maps file names to their text (default: the files in the tree)."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2201_01257_amd", "csrc")
     for name in ("kernels.hip", "device_util.h", "internal.h", "plan.cpp"):
+        if texts is not None:
+            text = texts[name]
+        else:
+            with open(os.path.join(csrc, name), encoding="utf-8") as fh:
+                text = fh.read()
         h.update(name.encode())
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(fh.read())
+        h.update(_code_only(text).encode())
     return h.hexdigest()
 
 

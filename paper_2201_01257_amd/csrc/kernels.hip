@@ -85,18 +85,18 @@ hipError_t launch_screen(const ScreenParams& p, hipStream_t s) {
 // runs over the pairs and, inside a pair, over chunks of KT flattened K indices.  Each chunk is
 // gathered from the operand blocks through the plan's offset tables straight into LDS; the
 // thread-to-element mapping follows the operand's stride-1 label (lanes along k when it is a
-// summed label, along m/n otherwise) so that global reads coalesce.  Both operands sit in LDS as
-// [row][k] with an odd row stride of KT+1 doubles, so that 16 consecutive rows (or k positions)
-// touch 16 distinct bank pairs: the gather stores and the MFMA operand reads are conflict-free.
-// There is no separate permutation pass.
+// summed label, along m/n otherwise) so that global reads coalesce.  Each operand chunk sits in
+// LDS in the layout LdsLayout chooses for its orientation and size, which keeps the MFMA operand
+// reads and the gather stores free of bank conflicts.  There is no separate permutation pass.
 //
 // Software pipeline with one barrier per chunk: LDS holds two chunk buffers.  While the MFMAs
 // of chunk c run from one buffer, the registers holding chunk c+1 (loaded during the previous
 // chunk's MFMAs) are stored into the other buffer, the global loads of chunk c+2 are issued into
 // the same registers, and the offset-table entries of chunk c+3 are fetched.  Inside a chunk the
-// MFMA operands of k-step s+1 are read from LDS while the MFMAs of step s run.  Every MFMA
-// block of the tile runs (padding rows, columns and k positions hold zeros), so the MFMA stream
-// has no branches.
+// MFMA operands of k-step s+1 are read from LDS while the MFMAs of step s run.  In a tile inside
+// its block every MFMA block runs (padding k positions hold zeros) and the MFMA stream has no
+// branches; a tile that runs past its block deals its live output fragments over the waves
+// (see below).
 //
 // v_mfma_f64_16x16x4_f64 lane layout (gfx950, checked on the device): A[m][k] comes from lane
 // m + 16k, B[k][n] from lane n + 16k, and D[m][n] lands in lane n + 16*(m%4), register m/4.
