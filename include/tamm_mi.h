@@ -236,7 +236,8 @@ const char* tamm_config_name(int32_t precision, int32_t config);
 /* Autotuner.  Measures every kernel configuration with K splits 1, 2, 4 and 8 that fits the
  * given workspace (hipEvents on stream; after one warm-up, the fastest of `reps` individually
  * timed executions counts; reps <= 0 means 3), then both tile orders with die chunks of 0, 16, 32,
- * 64 and 128 items (tamm_plan_set_order) for the fastest, keeps the fastest, and leaves the plan configured
+ * 64 and 128 items (tamm_plan_set_order) for the three fastest, then times the three fastest
+ * candidates of all these again in turn (three rounds) and keeps the lowest median, and leaves the plan configured
  * and bound to `workspace`.  With K splits s > 1 the tiles of the blocks with the largest summed
  * K extent are split into s parts and lighter blocks' tiles into proportionally fewer (at least
  * one), so the parts cost about the same.  The
