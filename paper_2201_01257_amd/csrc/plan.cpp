@@ -1093,6 +1093,20 @@ struct CacheEntry {
   double ms;
 };
 
+// The two timing events of an autotuner, destroyed on every exit path (HIP_TRY returns early).
+struct TimerEvents {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int create() {
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    return TAMM_OK;
+  }
+  ~TimerEvents() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
 bool cache_lookup(const char* path, uint64_t sig, const char* kind, CacheEntry& e) {
   if (!path || !*path) return false;
   std::ifstream f(path);
@@ -1144,9 +1158,9 @@ extern "C" int tamm_plan_autotune(tamm_plan* p, void* workspace, size_t bytes, v
   CacheEntry best{-1, 1, -1, 1e30};
   if (!cache_lookup(cache_path, p->signature, "plan2", best)) {
     if (reps <= 0) reps = 3;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    TimerEvents ev;
+    if ((rc = ev.create()) != TAMM_OK) return rc;
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     // one candidate: configure, bind, warm up, fastest of reps (alpha = 0, beta = 1 leaves out
     // unchanged for finite operands while doing the full work)
     auto trial = [&](int c, int ks, float* ms) -> int {
@@ -1190,6 +1204,7 @@ extern "C" int tamm_plan_autotune(tamm_plan* p, void* workspace, size_t bytes, v
       for (const CacheEntry& cand : ranked)
         for (int order : {0, 1})
           for (int ch : {0, 16, 32, 64, 128}) {
+            if (rc != TAMM_OK) break;  // a failed trial ends the search with its error
             p->xcd_chunk = ch;
             p->tile_order = order;
             float ms = 0;
@@ -1234,8 +1249,6 @@ extern "C" int tamm_plan_autotune(tamm_plan* p, void* workspace, size_t bytes, v
         }
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc != TAMM_OK) return rc;
     if (best.config < 0) return fail(TAMM_ERR_WORKSPACE, "no configuration fits the %zu-byte workspace", bytes);
     cache_store(cache_path, p->signature, "plan2", best);
@@ -1808,13 +1821,14 @@ int group_autotune(tamm_group* g, hipStream_t s, const char* cache_path, int32_t
     if (reps <= 0) reps = 3;
     for (int c = 0; c < kLayouts; ++c) best[c] = CacheEntry{-1, 1, 0, 1e30};
     std::vector<double> a0(g->nodes.size(), 0.0), b1(g->nodes.size(), 1.0);
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    TimerEvents ev;
+    if ((rc = ev.create()) != TAMM_OK) return rc;
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     int cus = 256, dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     for (int k = 0; k < f64_config_count() && rc == TAMM_OK; ++k) {
       for (int mult : {0, 1, 2, 4}) {  // 0: every resident slot (occupancy-sized grid)
+        if (rc != TAMM_OK) break;  // a failed launch ends the search with its error
         if ((rc = group_configure(g, k)) != TAMM_OK) break;
         if (g->ws_size > bytes) continue;
         for (int c = 0; c < kLayouts; ++c) g->grid[c] = mult * cus;
@@ -1837,8 +1851,6 @@ int group_autotune(tamm_group* g, hipStream_t s, const char* cache_path, int32_t
         }
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc != TAMM_OK) return rc;
     for (int c = 0; c < kLayouts; ++c)
       if (g->cls_begin[c + 1] != g->cls_begin[c] && best[c].config < 0)
