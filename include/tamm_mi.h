@@ -236,13 +236,13 @@ const char* tamm_config_name(int32_t precision, int32_t config);
 /* Autotuner.  Measures every kernel configuration with K splits 1, 2, 4 and 8 that fits the
  * given workspace (hipEvents on stream; after one warm-up, the fastest of `reps` individually
  * timed executions counts; reps <= 0 means 3), then both tile orders with die chunks of 0, 16, 32,
- * 64 and 128 items (tamm_plan_set_order) for the three fastest, then times the three fastest
- * candidates of all these again in turn (three rounds) and keeps the lowest median, and leaves the plan configured
- * and bound to `workspace`.  With K splits s > 1 the tiles of the blocks with the largest summed
- * K extent are split into s parts and lighter blocks' tiles into proportionally fewer (at least
- * one), so the parts cost about the same.  The
- * trial executions run with alpha = 0, beta = 1, so out keeps its values when the operands are
- * finite.  With a non-empty cache_path the result is appended to that text file keyed by the
+ * 64 and 128 items (tamm_plan_set_order) for the three fastest of those, then times the three
+ * fastest candidates of both passes again in turn (three rounds) and keeps the lowest median;
+ * it leaves the plan configured and bound to `workspace`.  The first failing HIP call or launch
+ * ends the search and its error is returned.  With K splits s > 1 the tiles of the blocks with
+ * the largest summed K extent are split into s parts and lighter blocks' tiles into
+ * proportionally fewer (at least one), so the parts cost about the same.  The trial executions
+ * run with alpha = 0, beta = 1, so out keeps its values when the operands are finite.  With a non-empty cache_path the result is appended to that text file keyed by the
  * plan's structural signature, and a later call with the same structure reuses it without
  * measuring.  tamm_plan_autotune_workspace_size gives the largest workspace any candidate needs.
  * Synchronises the stream. */
