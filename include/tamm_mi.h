@@ -447,14 +447,24 @@ int tamm_add_destroy(tamm_add* a);
  *     a tensor the chain reads, joins that chain: the chain is one node whose output tiles each
  *     run one K loop over the pairs of every member (same-output fusion).  Members must share
  *     alpha; a term whose coefficient differs is fused by scaling one of its operands upstream.
+ *   - AddOp chains: an AddOp with beta = 1 whose output was last touched by an AddOp (or a chain
+ *     of them) into the same output tensor joins that chain when its input's storage lies apart
+ *     from the output, the output has rank >= 2, no operation queued in between writes a tensor
+ *     the chain reads, the chain has fewer than 8 members, and its input ends (stride-1 label) in
+ *     the output's last label or in the one other label that the chain's transposed members end
+ *     in.  A chain is one node and one launch: out = beta_first*out + the members' alpha*in terms
+ *     added in queue order, each output element read and written once (the antisymmetrisers
+ *     P(ij)P(ab) written as permuted additions, Fig. 3).  Each product and partial sum is rounded
+ *     once, as in the AddOps run one by one; the device may fuse a product into its sum.
  *   - levels: nodes, in the order of their last queued operation, each go one level after the
  *     latest earlier node they conflict with (tensors compared by handle and by storage overlap).
  *   Every level runs as one group launch of its contraction nodes (screening, one persistent
- *   contraction launch per gather layout class) followed by its element-wise operations; the
- *   result equals running the queue in program order.
+ *   contraction launch per gather layout class) followed by its element-wise nodes; the
+ *   result equals running the queue in program order (up to the rounding of fused sums).
  * tamm_sched_workspace_size / _bind_workspace: one caller-owned device workspace (256-byte
- *   aligned) for every level's group, sized so that the autotuner's candidates fit; binding
- *   copies the static tables in (synchronous).
+ *   aligned) for every level's group, sized so that the autotuner's candidates fit, and for the
+ *   work items of every AddOp chain; binding copies the static tables in (synchronous).  Executing
+ *   a chain fails with ERR_ARG if an input was rebound onto storage that overlaps its output.
  * tamm_sched_autotune: the group autotuner (tamm_group_autotune) on every level (outputs left
  *   unchanged for finite inputs; synchronises the stream).
  * tamm_sched_execute: enqueue every level on stream.  If a graph was captured and every tensor

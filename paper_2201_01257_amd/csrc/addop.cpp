@@ -153,6 +153,73 @@ int add_enqueue(tamm_add* a, double alpha, double beta, hipStream_t s) {
 const tamm_tensor* add_out(const tamm_add* a) { return a->out; }
 const tamm_tensor* add_in(const tamm_add* a) { return a->in; }
 
+// True when AddOp b can join a chain of AddOps into the same out whose transposed terms read
+// through out dimension *ydim (-1: none so far): same out tensor, rank >= 2, in storage apart from
+// out, and b's in ending in out's last label or in label *ydim.  Updates *ydim.
+bool add_chain_accepts(const tamm_add* head, const tamm_add* b, int* ydim) {
+  if (b->out != head->out || b->out->rank < 2) return false;
+  if (b->out->bound && b->in->bound && b->out->numel > 0 && b->in->numel > 0) {
+    const char* o0 = (const char*)b->out->dev;
+    const char* i0 = (const char*)b->in->dev;
+    if (o0 < i0 + b->in->numel * 8 && i0 < o0 + b->out->numel * 8) return false;
+  } else if ((const void*)b->in == (const void*)b->out) {
+    return false;
+  }
+  if (b->ydim < 0) return true;
+  if (*ydim >= 0 && *ydim != b->ydim) return false;
+  *ydim = b->ydim;
+  return true;
+}
+
+// Work items of a chain: 32 x 32 tiles of the (ydim, last) plane of every out block.
+int add_chain_items(const tamm_add* head, int ydim, std::vector<AddItem>& items) {
+  const int r = head->out->rank;
+  items.clear();
+  for (size_t b = 0; b < head->blocks.size(); ++b) {
+    const AddBlock& B = head->blocks[b];
+    int64_t n = 1;
+    for (int d = 0; d < r; ++d) n *= B.ext[d];
+    const int ey = B.ext[ydim], ex = B.ext[r - 1];
+    const int64_t nbatch = n / ((int64_t)ey * ex);
+    for (int64_t t = 0; t < nbatch; ++t)
+      for (int y = 0; y < ey; y += 32)
+        for (int x = 0; x < ex; x += 32) items.push_back(AddItem{(int32_t)b, (int32_t)t, y, x});
+    if (items.size() > (size_t)INT32_MAX) return fail(TAMM_ERR_UNSUPPORTED, "too many work items");
+  }
+  return TAMM_OK;
+}
+
+// Enqueue a chain: out = beta*out + sum_t alpha[t]*in_t (items from add_chain_items, on device).
+int add_chain_enqueue(const std::vector<tamm_add*>& m, const std::vector<double>& alpha, double beta, int ydim,
+                      const AddItem* items, int64_t n_items, hipStream_t s) {
+  if (m.empty() || m.size() > (size_t)kMaxAddTerms || alpha.size() != m.size())
+    return fail(TAMM_ERR_ARG, "an AddOp chain has 1 to %d members", kMaxAddTerms);
+  AddMultiParams p{};
+  p.out = m[0]->out->dev;
+  for (size_t t = 0; t < m.size(); ++t) {
+    const tamm_add* a = m[t];
+    if (!a->bound) return fail(TAMM_ERR_UNBOUND, "AddOp workspace is not bound");
+    if (!a->out->bound || !a->in->bound) return fail(TAMM_ERR_UNBOUND, "tensor storage not bound");
+    const char* o0 = (const char*)a->out->dev;
+    const char* i0 = (const char*)a->in->dev;
+    if (a->out != m[0]->out || (a->out->numel > 0 && a->in->numel > 0 && o0 < i0 + a->in->numel * 8 && i0 < o0 + a->out->numel * 8))
+      return fail(TAMM_ERR_ARG, "an AddOp chain needs one out and inputs apart from it");
+    if (a->ydim >= 0 && a->ydim != ydim) return fail(TAMM_ERR_ARG, "AddOp chain member reads through another dimension");
+    p.in[t] = a->in->dev;
+    p.blocks[t] = (const AddBlock*)(a->ws + a->off_blocks);
+    p.alpha[t] = alpha[t];
+    p.trans[t] = a->ydim >= 0 ? 1 : 0;
+  }
+  p.items = items;
+  p.n_items = n_items;
+  p.beta = beta;
+  p.rank = m[0]->out->rank;
+  p.ydim = ydim;
+  p.nterms = (int32_t)m.size();
+  HIP_TRY(launch_add_multi(p, s));
+  return TAMM_OK;
+}
+
 }  // namespace tamm
 
 extern "C" int tamm_add_execute(tamm_add* a, double alpha, double beta, void* stream) {

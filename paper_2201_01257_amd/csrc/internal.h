@@ -200,6 +200,26 @@ struct AddParams {
 };
 
 hipError_t launch_add(const AddParams& p, hipStream_t s);
+
+// A chain of AddOps into one out (the scheduler's fused element-wise node): out = beta*out +
+// sum_t alpha_t*in_t(permuted), out read and written once.  Every term shares out's block list
+// (blocks[t][b] describes out block b for term t).  Items are transpose-mode tiles of the
+// (ydim, last) plane; trans[t] = 1 when in_t's last label is out dimension ydim (read through the
+// LDS tile), 0 when it is out's last label (read directly).
+constexpr int kMaxAddTerms = 8;
+struct AddMultiParams {
+  double* out;
+  const double* in[kMaxAddTerms];
+  const AddBlock* blocks[kMaxAddTerms];
+  double alpha[kMaxAddTerms];
+  int32_t trans[kMaxAddTerms];
+  const AddItem* items;
+  int64_t n_items;
+  double beta;
+  int32_t rank, ydim, nterms, pad;
+};
+
+hipError_t launch_add_multi(const AddMultiParams& p, hipStream_t s);
 // SetOp: p[0 .. n) = value.
 hipError_t launch_fill(double* p, int64_t n, double value, hipStream_t s);
 

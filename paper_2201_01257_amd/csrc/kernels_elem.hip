@@ -147,6 +147,97 @@ __global__ __launch_bounds__(256) void k_add_transpose(AddParams P) {
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// AddOp chain (several AddOps into one out, fused by the scheduler): one 32 x 32 tile of the
+// (ydim, last) plane per workgroup, as in k_add_transpose.  Every term's loads are issued before
+// any is used; a term whose in ends in out's last label is read along it, one whose in ends in
+// label ydim goes through the LDS tile.  The terms are added to beta*out in queue order.
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_add_multi(AddMultiParams P) {
+  __shared__ double tile[kAddTile][kAddTile + 1];
+  const int64_t it = blockIdx.x;
+  if (it >= P.n_items) return;
+  const AddItem item = P.items[it];
+  const int r = P.rank, yd = P.ydim, xd = r - 1;
+  const AddBlock& B0 = P.blocks[0][item.block];  // out geometry, the same for every term
+  int ostr[kMaxRank], idx[kMaxRank];
+  int s = 1;
+  for (int d = r - 1; d >= 0; --d) {
+    ostr[d] = s;
+    s *= B0.ext[d];
+  }
+  int rem = item.a;
+  int64_t obase = B0.out_off;
+  for (int d = r - 1; d >= 0; --d) {
+    idx[d] = 0;
+    if (d == yd || d == xd) continue;
+    idx[d] = rem % B0.ext[d];
+    rem /= B0.ext[d];
+    obase += (int64_t)idx[d] * ostr[d];
+  }
+  const int ey = B0.ext[yd], ex = B0.ext[xd];
+  const int l = threadIdx.x % kAddTile, k0 = threadIdx.x / kAddTile;  // 8 rows per pass
+  constexpr int kPasses = kAddTile / 8;
+  // loads of every term: direct terms at the out element (y0 + k0 + 8q, x0 + l), lanes along x;
+  // transposed terms at (y0 + l, x0 + k0 + 8q), lanes along y (in's stride-1 label)
+  double v[kMaxAddTerms][kPasses];
+#pragma unroll
+  for (int t = 0; t < kMaxAddTerms; ++t) {
+#pragma unroll
+    for (int q = 0; q < kPasses; ++q) v[t][q] = 0.0;
+    if (t >= P.nterms) continue;
+    const AddBlock& B = P.blocks[t][item.block];
+    if (B.in_off < 0) continue;  // block not stored in this term's input: adds zero
+    int64_t ibase = B.in_off;
+    for (int d = 0; d < r; ++d)
+      if (d != yd && d != xd) ibase += (int64_t)idx[d] * B.istr[d];
+    const double* __restrict__ in = P.in[t] + ibase;
+#pragma unroll
+    for (int q = 0; q < kPasses; ++q) {
+      const int k = k0 + 8 * q;
+      if (P.trans[t]) {
+        const int y = item.b + l, x = item.c + k;
+        if (y < ey && x < ex) v[t][q] = in[y + (int64_t)x * B.istr[xd]];
+      } else {
+        const int y = item.b + k, x = item.c + l;
+        if (y < ey && x < ex) v[t][q] = in[(int64_t)y * B.istr[yd] + x];
+      }
+    }
+  }
+  double acc[kPasses];
+#pragma unroll
+  for (int q = 0; q < kPasses; ++q) {
+    const int y = item.b + k0 + 8 * q, x = item.c + l;
+    acc[q] = (P.beta != 0.0 && y < ey && x < ex) ? P.beta * P.out[obase + (int64_t)y * ostr[yd] + x] : 0.0;
+  }
+  // transposed terms through the tile, one after another; then every term into the sum
+#pragma unroll
+  for (int t = 0; t < kMaxAddTerms; ++t) {
+    if (t >= P.nterms) continue;
+    if (P.trans[t]) {
+      __syncthreads();  // the previous term's reads of the tile are done
+#pragma unroll
+      for (int q = 0; q < kPasses; ++q) tile[k0 + 8 * q][l] = v[t][q];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kPasses; ++q) v[t][q] = tile[l][k0 + 8 * q];
+    }
+#pragma unroll
+    for (int q = 0; q < kPasses; ++q) acc[q] += P.alpha[t] * v[t][q];
+  }
+#pragma unroll
+  for (int q = 0; q < kPasses; ++q) {
+    const int y = item.b + k0 + 8 * q, x = item.c + l;
+    if (y < ey && x < ex) P.out[obase + (int64_t)y * ostr[yd] + x] = acc[q];
+  }
+}
+
+hipError_t launch_add_multi(const AddMultiParams& p, hipStream_t s) {
+  if (p.n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add_multi, dim3((unsigned)p.n_items), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
 hipError_t launch_add(const AddParams& p, hipStream_t s) {
   if (p.n_items <= 0) return hipSuccess;
   const dim3 g((unsigned)p.n_items), b(256);

@@ -1,10 +1,11 @@
 // Host side of the C ABI, part 5: the scheduler.  Operations are queued (SetOp, AddOp, MultOp and
 // the denominator update), then analysed once: contractions that only accumulate into the output
-// of the previous contraction are fused with it into one node (their pairs share output tiles), a
-// dataflow analysis over the tensors each node reads and writes assigns every node to the first
-// level after all the nodes it conflicts with, and each level runs as one grouped launch of its
-// contraction nodes plus its element-wise operations.  The whole schedule can be captured into one
-// hipGraph and replayed.
+// of the previous contraction are fused with it into one node (their pairs share output tiles),
+// and so are AddOps that only accumulate into the output of the previous AddOp (one launch reads
+// and writes that output once for all of them); a dataflow analysis over the tensors each node
+// reads and writes assigns every node to the first level after all the nodes it conflicts with,
+// and each level runs as one grouped launch of its contraction nodes plus its element-wise
+// nodes.  The whole schedule can be captured into one hipGraph and replayed.
 #include <algorithm>
 #include <cstring>
 #include <memory>
@@ -31,13 +32,16 @@ struct Op {
 };
 
 struct Node {
-  std::vector<int> ops;  // queued operations, in queue order (several: a fused contraction)
+  std::vector<int> ops;  // queued operations, in queue order (several: a fused contraction or AddOp chain)
   int level = -1;
+  int add_ydim = -1;               // AddOp chain: out dimension of its transposed terms' last label
+  std::vector<AddItem> add_items;  // AddOp chain: work items, uploaded at bind time
+  size_t items_off = 0;
 };
 
 struct Level {
   std::vector<int> contract_nodes;  // nodes run as one group
-  std::vector<int> elem_ops;        // element-wise operations, queue order
+  std::vector<int> elem_nodes;      // element-wise nodes, queue order
   tamm_group* group = nullptr;
   std::vector<double> alpha, beta;  // per group node
   size_t ws_off = 0, ws_size = 0;
@@ -199,6 +203,34 @@ extern "C" int tamm_sched_build(tamm_sched* s) {
         }
       }
     }
+    if (op.kind == OP_ADD && op.beta == 1.0) {
+      int last = -1;  // last earlier operation touching op.out
+      for (int k = (int)j - 1; k >= 0 && last < 0; --k) {
+        const Op& o = s->ops[k];
+        if (same_storage(o.out, op.out) || touches(o.reads, op.out)) last = k;
+      }
+      if (last >= 0 && s->ops[last].kind == OP_ADD && s->ops[last].out == op.out) {
+        const int head_node = chain_of[last];
+        Node& chain = s->nodes[head_node];
+        const tamm_add* head = s->ops[chain.ops[0]].add;
+        int ydim = chain.add_ydim;
+        bool ok_fuse = (int)chain.ops.size() < kMaxAddTerms;
+        if (ok_fuse && chain.ops.size() == 1) ok_fuse = add_chain_accepts(head, head, &ydim);
+        ok_fuse = ok_fuse && add_chain_accepts(head, op.add, &ydim);
+        std::vector<const tamm_tensor*> cr, cw;
+        node_io(s, chain, cr, cw);
+        for (int k = chain.ops[0] + 1; k < (int)j && ok_fuse; ++k) {
+          if (chain_of[k] == head_node) continue;
+          if (touches(cr, s->ops[k].out)) ok_fuse = false;
+        }
+        if (ok_fuse) {
+          chain.ops.push_back((int)j);
+          chain.add_ydim = ydim;
+          chain_of[j] = head_node;
+          continue;
+        }
+      }
+    }
     chain_of[j] = (int)s->nodes.size();
     s->nodes.push_back(Node{{(int)j}, -1});
   }
@@ -225,7 +257,7 @@ extern "C" int tamm_sched_build(tamm_sched* s) {
     const Node& n = s->nodes[order[x]];
     Level& L = s->levels[n.level];
     if (s->ops[n.ops[0]].kind == OP_CONTRACT) L.contract_nodes.push_back(order[x]);
-    else L.elem_ops.push_back(n.ops[0]);
+    else L.elem_nodes.push_back(order[x]);
   }
   // ---- one group per level with contractions; workspace regions sized for the autotuner
   size_t off = 0;
@@ -248,6 +280,21 @@ extern "C" int tamm_sched_build(tamm_sched* s) {
     L.ws_off = align256(off);
     L.ws_size = group_autotune_workspace_size(L.group);
     off = L.ws_off + L.ws_size;
+  }
+  // ---- AddOp chains: work items over the (ydim, last) plane (ydim: rank - 2 when every term
+  // reads directly), in their own workspace regions
+  for (Node& n : s->nodes) {
+    if (n.ops.size() < 2 || s->ops[n.ops[0]].kind != OP_ADD) continue;
+    const tamm_add* head = s->ops[n.ops[0]].add;
+    if (n.add_ydim < 0) n.add_ydim = add_out(head)->rank - 2;
+    const int rc = add_chain_items(head, n.add_ydim, n.add_items);
+    if (rc != TAMM_OK) {
+      sched_free(s);
+      s->nodes.clear();
+      return rc;
+    }
+    n.items_off = align256(off);
+    off = n.items_off + n.add_items.size() * sizeof(AddItem);
   }
   s->ws_size = std::max<size_t>(align256(off), 256);
   s->built = true;
@@ -272,6 +319,10 @@ extern "C" int tamm_sched_bind_workspace(tamm_sched* s, void* ws, size_t bytes) 
     const int rc = group_bind_ws(L.group, (char*)ws + L.ws_off, L.ws_size);
     if (rc != TAMM_OK) return rc;
   }
+  for (const Node& n : s->nodes)
+    if (!n.add_items.empty())
+      HIP_TRY(hipMemcpy((char*)ws + n.items_off, n.add_items.data(), n.add_items.size() * sizeof(AddItem),
+                        hipMemcpyHostToDevice));
   s->ws = (char*)ws;
   s->ws_bytes = bytes;
   s->bound = true;
@@ -321,8 +372,21 @@ static int sched_enqueue(tamm_sched* s, hipStream_t st) {
       const int rc = group_enqueue(L.group, st);
       if (rc != TAMM_OK) return rc;
     }
-    for (int i : L.elem_ops) {
-      const Op& op = s->ops[i];
+    for (int q : L.elem_nodes) {
+      const Node& n = s->nodes[q];
+      if (n.ops.size() > 1) {  // AddOp chain: the head's beta, then every member's term
+        std::vector<tamm_add*> m;
+        std::vector<double> alpha;
+        for (int i : n.ops) {
+          m.push_back(s->ops[i].add);
+          alpha.push_back(s->ops[i].alpha);
+        }
+        const int rc = add_chain_enqueue(m, alpha, s->ops[n.ops[0]].beta, n.add_ydim,
+                                         (const AddItem*)(s->ws + n.items_off), (int64_t)n.add_items.size(), st);
+        if (rc != TAMM_OK) return rc;
+        continue;
+      }
+      const Op& op = s->ops[n.ops[0]];
       int rc = TAMM_OK;
       switch (op.kind) {
         case OP_SET:

@@ -112,3 +112,69 @@ def test_add_label_errors():
         tm.Add(x, "abij", x, "abik")
     with pytest.raises(tm.TammError):
         tm.Add(x, "abij", y, "abij")  # b binds o in y
+
+
+def _chain_bound(ref0, terms, beta):
+    """Element-wise bound of a chain against the oracle's one-by-one AddOps: each side rounds
+    every product and every partial sum once (the device may fuse a product into its sum), so
+    both lie within (terms + 2) units in the last place of sum |beta*out| + sum |alpha*x|."""
+    scale = {t: np.abs(beta * b) for t, b in ref0.blocks.items()}
+    for inp_o, out_lbl, in_lbl, alpha in terms:
+        ax = oracle.add(ref0, out_lbl, inp_o, in_lbl, alpha, 0.0)
+        for t in scale:
+            scale[t] = scale[t] + np.abs(ax.blocks[t])
+    return {t: 2.0 ** -52 * (len(terms) + 2) * s + 1e-300 for t, s in scale.items()}
+
+
+def _odd_tiles_dropped(tiles, spins):
+    # a predicate of its own for one input: the spin rule, minus blocks with an odd first tile
+    return sum(spins[: len(spins) // 2]) == sum(spins[len(spins) // 2:]) and tiles[0] % 2 == 0
+
+
+@pytest.mark.parametrize("case", ["antisymmetriser", "first_virtual", "direct_only", "rank2"])
+def test_scheduled_addop_chain_matches_oracle(case):
+    # the scheduler runs consecutive AddOps into one out as one launch (an AddOp chain); ragged
+    # tiles on both spaces, terms read directly and through the LDS tile, beta of the first term;
+    # tile extents above 32 put several 32 x 32 work items on one plane of a block
+    prob = {"antisymmetriser": Problem(14, 22, 4, 5), "first_virtual": Problem(12, 90, 3, 37),
+            "direct_only": Problem(76, 20, 35, 10), "rank2": Problem(76, 90, 35, 37)}[case]
+    if case == "rank2":
+        out, out_o = dense_pair(prob, "vo", 11)
+        x, x_o = dense_pair(prob, "vo", 12)
+        y, y_o = dense_pair(prob, "ov", 13)
+        terms = [(x, x_o, "ai", "ai", 0.5, -1.5), (y, y_o, "ai", "ia", -2.0, 1.0), (x, x_o, "ai", "ai", 0.25, 1.0)]
+    else:
+        out, out_o = dense_pair(prob, "vvoo", 11)
+        x, x_o = dense_pair(prob, "vvoo", 12)
+        z, z_o = dense_pair(prob, "vvoo", 13)
+        if case == "antisymmetriser":  # the doubles residual's P(ij)P(ab) terms
+            terms = [(x, x_o, "abij", "abij", 1.0, 0.0), (x, x_o, "abij", "abji", -1.0, 1.0),
+                     (x, x_o, "abij", "baij", -1.0, 1.0), (x, x_o, "abij", "baji", 1.0, 1.0),
+                     (z, z_o, "abij", "abij", 0.5, 1.0), (z, z_o, "abij", "abji", -0.5, 1.0)]
+        elif case == "first_virtual":  # transposed terms end in out's first label
+            w, w_o = dense_pair(prob, "oovv", 14)
+            dense = np.random.default_rng(15).standard_normal(tuple(s.extent for s in w_o.spaces))
+            q = tm.Tensor([prob.g[c] for c in "oovv"], nonzero=_odd_tiles_dropped).from_dense(dense)
+            q_o = oracle.BlockTensor.from_dense([prob.o[c] for c in "oovv"], dense, nonzero=_odd_tiles_dropped)
+            terms = [(x, x_o, "abij", "baij", 2.0, 0.75), (w, w_o, "abij", "ijba", -1.0, 1.0),
+                     (q, q_o, "abij", "jiba", 1.5, 1.0)]
+        else:
+            terms = [(x, x_o, "abij", "abij", 1.0, 1.0), (z, z_o, "abij", "baij", -3.0, 1.0),
+                     (x, x_o, "abij", "baij", 0.5, 1.0)]
+    lbl = terms[0][2]
+    s = tm.Scheduler()
+    for g, _, ol, il, alpha, beta in terms:
+        s.add(tm.Add(out, ol, g, il), alpha, beta)
+    s.build()
+    assert s.info()["nodes"] == 1 and s.info()["fused_ops"] == len(terms)
+    s.bind_workspace(out.data.device)
+    s.execute()
+    torch.cuda.synchronize()
+    ref = out_o
+    for _, o, ol, il, alpha, beta in terms:
+        ref = oracle.add(ref, ol, o, il, alpha, beta)
+    bound = _chain_bound(out_o, [(o, ol, il, alpha) for _, o, ol, il, alpha, _ in terms], terms[0][5])
+    got = out.to_blocks()
+    assert lbl and ref.blocks
+    for t, r in ref.blocks.items():
+        assert np.all(np.abs(got[t] - r) <= bound[t]), (case, t)

@@ -46,15 +46,16 @@ def test_doubles_iteration_fusion_and_levels():
     s, _ = doubles_iteration_queue()
     s.build()
     info = s.info()
-    assert info["fused_ops"] == 2                 # ladder + hole-hole ladder share output tiles
-    assert info["nodes"] == 13                    # 14 operations, two of them in one node
+    # ladder + hole-hole ladder share output tiles; the eight AddOps into R form one chain
+    assert info["fused_ops"] == 2 + 8
+    assert info["nodes"] == 6                     # 14 operations: W, the ladders, X, Zv, Zo, the chain
     lv = [s.op_info(i)[0] for i in range(14)]
     nd = [s.op_info(i)[1] for i in range(14)]
-    assert nd[1] == nd[2] and len(set(nd)) == 13
+    assert nd[1] == nd[2] and len(set(nd[6:])) == 1 and len(set(nd)) == 6
     assert lv[0] == 0 and lv[3] == 0 and lv[4] == 0 and lv[5] == 0   # independent terms together
     assert lv[1] == lv[2] == 1                    # after W (read by the hole-hole ladder)
-    assert lv[6:] == [2, 3, 4, 5, 6, 7, 8, 9]     # every AddOp writes R: one after another
-    assert info["levels"] == 10
+    assert lv[6:] == [2] * 8                      # one launch after the ladders wrote R
+    assert info["levels"] == 3
     with pytest.raises(tm.TammError):
         s.set(tm.Tensor(list(spaces()), device=None), 1.0)  # no queueing after build
 
@@ -85,6 +86,63 @@ def test_no_fusion_when_alpha_differs_or_inputs_change_in_between():
     s.build()
     assert s.info()["fused_ops"] == 2
     assert [s.op_info(i)[0] for i in range(3)] == [1, 0, 1]
+
+
+def test_addop_chains_and_where_they_break():
+    o, v = spaces()
+    R, X, Y, Z = tensor(o, v, "vvoo"), tensor(o, v, "vvoo"), tensor(o, v, "oovv"), tensor(o, v, "vvoo")
+
+    def nodes_levels(s, n):
+        s.build()
+        return [s.op_info(i)[1] for i in range(n)], [s.op_info(i)[0] for i in range(n)]
+
+    # a head with beta = 0, then accumulating terms read directly (baij) and through the second
+    # occupied label (abji, baji): one node
+    s = tm.Scheduler()
+    for lbl, beta in (("abij", 0.0), ("baij", 1.0), ("abji", 1.0), ("baji", 1.0)):
+        s.add(tm.Add(R, "abij", X, lbl, bind=False), 1.0, beta)
+    nd, lv = nodes_levels(s, 4)
+    assert len(set(nd)) == 1 and lv == [0] * 4 and s.info()["fused_ops"] == 4
+    # beta != 1 starts a new chain (whose direct head then takes a term read through out
+    # dimension 1); so does a term read through another dimension than the chain's (ijab ends in
+    # b, out dimension 1, after abji fixed dimension 2)
+    s = tm.Scheduler()
+    s.add(tm.Add(R, "abij", X, "abji", bind=False), 1.0, 1.0)
+    s.add(tm.Add(R, "abij", X, "abij", bind=False), 1.0, 0.5)
+    s.add(tm.Add(R, "abij", Y, "ijab", bind=False), 1.0, 1.0)
+    nd, lv = nodes_levels(s, 3)
+    assert nd[0] != nd[1] and nd[1] == nd[2] and lv == [0, 1, 1]
+    s = tm.Scheduler()
+    s.add(tm.Add(R, "abij", X, "abji", bind=False), 1.0, 1.0)
+    s.add(tm.Add(R, "abij", Y, "ijab", bind=False), 1.0, 1.0)
+    s.add(tm.Add(R, "abij", X, "abij", bind=False), 1.0, 1.0)
+    nd, lv = nodes_levels(s, 3)
+    assert nd[0] != nd[1] and nd[1] == nd[2] and lv == [0, 1, 1]
+    # an operation in between writes what the chain reads: no fusion
+    s = tm.Scheduler()
+    s.add(tm.Add(R, "abij", X, "abij", bind=False), 1.0, 1.0)
+    s.set(X, 2.0)
+    s.add(tm.Add(R, "abij", Z, "baij", bind=False), 1.0, 1.0)
+    nd, lv = nodes_levels(s, 3)
+    assert len(set(nd)) == 3 and lv == [0, 1, 1]  # the second term needs only the first
+    # ... but an operation in between that writes only the new member's input does not stop it
+    s = tm.Scheduler()
+    s.add(tm.Add(R, "abij", X, "abij", bind=False), 1.0, 1.0)
+    s.set(Z, 2.0)
+    s.add(tm.Add(R, "abij", Z, "baij", bind=False), 1.0, 1.0)
+    nd, lv = nodes_levels(s, 3)
+    assert nd[0] == nd[2] and lv == [1, 0, 1]
+    # out added to itself stays a node of its own; at most eight terms per chain
+    s = tm.Scheduler()
+    s.add(tm.Add(R, "abij", X, "abij", bind=False), 1.0, 1.0)
+    s.add(tm.Add(R, "abij", R, "abij", bind=False), 1.0, 1.0)
+    nd, _ = nodes_levels(s, 2)
+    assert nd[0] != nd[1]
+    s = tm.Scheduler()
+    for k in range(10):
+        s.add(tm.Add(R, "abij", X if k % 2 else Z, "abij", bind=False), 1.0, 1.0)
+    nd, lv = nodes_levels(s, 10)
+    assert nd[:8] == [nd[0]] * 8 and nd[8] == nd[9] != nd[0] and lv == [0] * 8 + [1] * 2
 
 
 def test_fusion_needs_the_same_row_column_split():
