@@ -171,9 +171,24 @@ bool add_chain_accepts(const tamm_add* head, const tamm_add* b, int* ydim) {
   return true;
 }
 
-// Work items of a chain: 32 x 32 tiles of the (ydim, last) plane of every out block.
-int add_chain_items(const tamm_add* head, int ydim, std::vector<AddItem>& items) {
+// Work items of a chain: whole planes of out's last two dimensions when ydim is the
+// second-to-last, every block's plane holds at most kAddPlaneMax elements and lies contiguous in
+// every member's input (*plane = true); otherwise 32 x 32 tiles of the (ydim, last) plane.
+int add_chain_items(const std::vector<const tamm_add*>& m, int ydim, std::vector<AddItem>& items, bool* plane) {
+  const tamm_add* head = m[0];
   const int r = head->out->rank;
+  bool pl = ydim == r - 2;
+  for (size_t b = 0; b < head->blocks.size() && pl; ++b) {
+    const int ey = head->blocks[b].ext[r - 2], ex = head->blocks[b].ext[r - 1];
+    if ((int64_t)ey * ex > kAddPlaneMax) pl = false;
+    for (const tamm_add* a : m) {
+      const AddBlock& B = a->blocks[b];
+      const bool contiguous = a->ydim < 0 ? (B.istr[r - 1] == 1 && B.istr[r - 2] == ex)
+                                          : (B.istr[r - 2] == 1 && B.istr[r - 1] == ey);
+      pl = pl && contiguous;
+    }
+  }
+  *plane = pl;
   items.clear();
   for (size_t b = 0; b < head->blocks.size(); ++b) {
     const AddBlock& B = head->blocks[b];
@@ -181,9 +196,14 @@ int add_chain_items(const tamm_add* head, int ydim, std::vector<AddItem>& items)
     for (int d = 0; d < r; ++d) n *= B.ext[d];
     const int ey = B.ext[ydim], ex = B.ext[r - 1];
     const int64_t nbatch = n / ((int64_t)ey * ex);
-    for (int64_t t = 0; t < nbatch; ++t)
+    for (int64_t t = 0; t < nbatch; ++t) {
+      if (pl) {
+        items.push_back(AddItem{(int32_t)b, (int32_t)t, 0, 0});
+        continue;
+      }
       for (int y = 0; y < ey; y += 32)
         for (int x = 0; x < ex; x += 32) items.push_back(AddItem{(int32_t)b, (int32_t)t, y, x});
+    }
     if (items.size() > (size_t)INT32_MAX) return fail(TAMM_ERR_UNSUPPORTED, "too many work items");
   }
   return TAMM_OK;
@@ -191,7 +211,7 @@ int add_chain_items(const tamm_add* head, int ydim, std::vector<AddItem>& items)
 
 // Enqueue a chain: out = beta*out + sum_t alpha[t]*in_t (items from add_chain_items, on device).
 int add_chain_enqueue(const std::vector<tamm_add*>& m, const std::vector<double>& alpha, double beta, int ydim,
-                      const AddItem* items, int64_t n_items, hipStream_t s) {
+                      bool plane, const AddItem* items, int64_t n_items, hipStream_t s) {
   if (m.empty() || m.size() > (size_t)kMaxAddTerms || alpha.size() != m.size())
     return fail(TAMM_ERR_ARG, "an AddOp chain has 1 to %d members", kMaxAddTerms);
   AddMultiParams p{};
@@ -216,6 +236,8 @@ int add_chain_enqueue(const std::vector<tamm_add*>& m, const std::vector<double>
   p.rank = m[0]->out->rank;
   p.ydim = ydim;
   p.nterms = (int32_t)m.size();
+  p.plane = plane ? 1 : 0;
+  if (plane && ydim != p.rank - 2) return fail(TAMM_ERR_ARG, "plane mode needs the last two dimensions");
   HIP_TRY(launch_add_multi(p, s));
   return TAMM_OK;
 }

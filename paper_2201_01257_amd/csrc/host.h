@@ -25,9 +25,9 @@ const tamm_tensor* add_out(const tamm_add* a);
 const tamm_tensor* add_in(const tamm_add* a);
 // AddOp chains (several AddOps into one out, one launch), built by the scheduler.
 bool add_chain_accepts(const tamm_add* head, const tamm_add* b, int* ydim);
-int add_chain_items(const tamm_add* head, int ydim, std::vector<AddItem>& items);
+int add_chain_items(const std::vector<const tamm_add*>& m, int ydim, std::vector<AddItem>& items, bool* plane);
 int add_chain_enqueue(const std::vector<tamm_add*>& m, const std::vector<double>& alpha, double beta, int ydim,
-                      const AddItem* items, int64_t n_items, hipStream_t s);
+                      bool plane, const AddItem* items, int64_t n_items, hipStream_t s);
 
 // Plans and groups (plan.cpp), shared with the scheduler.
 void plan_io(const tamm_plan* p, tamm_tensor** out, const tamm_tensor** lhs, const tamm_tensor** rhs, int* precision);

@@ -203,10 +203,13 @@ hipError_t launch_add(const AddParams& p, hipStream_t s);
 
 // A chain of AddOps into one out (the scheduler's fused element-wise node): out = beta*out +
 // sum_t alpha_t*in_t(permuted), out read and written once.  Every term shares out's block list
-// (blocks[t][b] describes out block b for term t).  Items are transpose-mode tiles of the
-// (ydim, last) plane; trans[t] = 1 when in_t's last label is out dimension ydim (read through the
-// LDS tile), 0 when it is out's last label (read directly).
+// (blocks[t][b] describes out block b for term t).  trans[t] = 1 when in_t's last label is out
+// dimension ydim (read through LDS), 0 when it is out's last label (read directly).  Items are
+// transpose-mode tiles of the (ydim, last) plane, or, with plane = 1 (ydim = rank - 2, every
+// input's last two labels are out's last two, planes of at most kAddPlaneMax elements), whole
+// planes: block and batch index over the other dimensions.
 constexpr int kMaxAddTerms = 8;
+constexpr int kAddPlaneMax = 1024;
 struct AddMultiParams {
   double* out;
   const double* in[kMaxAddTerms];
@@ -216,7 +219,7 @@ struct AddMultiParams {
   const AddItem* items;
   int64_t n_items;
   double beta;
-  int32_t rank, ydim, nterms, pad;
+  int32_t rank, ydim, nterms, plane;
 };
 
 hipError_t launch_add_multi(const AddMultiParams& p, hipStream_t s);

@@ -232,9 +232,86 @@ __global__ __launch_bounds__(256) void k_add_multi(AddMultiParams P) {
   }
 }
 
+// Plane mode of the AddOp chain (small planes, contiguous in every input): one workgroup per
+// plane, lanes along the flattened plane, so a direct term is one contiguous run of loads; a
+// transposed term (its plane stored [x][y]) is read contiguously too and turned through LDS,
+// stored with a row stride of ey + 1 doubles so that the transposed reads spread over the banks.
+__global__ __launch_bounds__(256) void k_add_multi_plane(AddMultiParams P) {
+  __shared__ double tile[2 * kAddPlaneMax];
+  const int64_t it = blockIdx.x;
+  if (it >= P.n_items) return;
+  const AddItem item = P.items[it];
+  const int r = P.rank, yd = r - 2, xd = r - 1;
+  const AddBlock& B0 = P.blocks[0][item.block];
+  const int ey = B0.ext[yd], ex = B0.ext[xd], n = ey * ex;
+  int idx[kMaxRank];
+  int rem = item.a;
+  for (int d = r - 3; d >= 0; --d) {
+    idx[d] = rem % B0.ext[d];
+    rem /= B0.ext[d];
+  }
+  const int64_t obase = B0.out_off + (int64_t)item.a * n;  // the plane is out's last two dimensions
+  constexpr int kPasses = kAddPlaneMax / 256;
+  double v[kMaxAddTerms][kPasses];
+#pragma unroll
+  for (int t = 0; t < kMaxAddTerms; ++t) {
+#pragma unroll
+    for (int q = 0; q < kPasses; ++q) v[t][q] = 0.0;
+    if (t >= P.nterms) continue;
+    const AddBlock& B = P.blocks[t][item.block];
+    if (B.in_off < 0) continue;  // block not stored in this term's input: adds zero
+    int64_t ibase = B.in_off;
+    for (int d = 0; d < r - 2; ++d) ibase += (int64_t)idx[d] * B.istr[d];
+    const double* __restrict__ in = P.in[t] + ibase;
+#pragma unroll
+    for (int q = 0; q < kPasses; ++q) {
+      const int f = (int)threadIdx.x + 256 * q;
+      if (f < n) v[t][q] = in[f];
+    }
+  }
+  double acc[kPasses];
+#pragma unroll
+  for (int q = 0; q < kPasses; ++q) {
+    const int f = (int)threadIdx.x + 256 * q;
+    acc[q] = (P.beta != 0.0 && f < n) ? P.beta * P.out[obase + f] : 0.0;
+  }
+#pragma unroll
+  for (int t = 0; t < kMaxAddTerms; ++t) {
+    if (t >= P.nterms) continue;
+    if (P.trans[t]) {
+      __syncthreads();  // the previous term's reads of the tile are done
+#pragma unroll
+      for (int q = 0; q < kPasses; ++q) {
+        const int f = (int)threadIdx.x + 256 * q;  // in's plane index: f = x*ey + y
+        if (f < n) {
+          const int x = f / ey, y = f - x * ey;
+          tile[x * (ey + 1) + y] = v[t][q];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kPasses; ++q) {
+        const int f = (int)threadIdx.x + 256 * q;  // out's plane index: f = y*ex + x
+        if (f < n) {
+          const int y = f / ex, x = f - y * ex;
+          v[t][q] = tile[x * (ey + 1) + y];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kPasses; ++q) acc[q] += P.alpha[t] * v[t][q];
+  }
+#pragma unroll
+  for (int q = 0; q < kPasses; ++q) {
+    const int f = (int)threadIdx.x + 256 * q;
+    if (f < n) P.out[obase + f] = acc[q];
+  }
+}
+
 hipError_t launch_add_multi(const AddMultiParams& p, hipStream_t s) {
   if (p.n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_add_multi, dim3((unsigned)p.n_items), dim3(256), 0, s, p);
+  if (p.plane) hipLaunchKernelGGL(k_add_multi_plane, dim3((unsigned)p.n_items), dim3(256), 0, s, p);
+  else hipLaunchKernelGGL(k_add_multi, dim3((unsigned)p.n_items), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 

@@ -35,6 +35,7 @@ struct Node {
   std::vector<int> ops;  // queued operations, in queue order (several: a fused contraction or AddOp chain)
   int level = -1;
   int add_ydim = -1;               // AddOp chain: out dimension of its transposed terms' last label
+  bool add_plane = false;          // AddOp chain: whole planes per work item
   std::vector<AddItem> add_items;  // AddOp chain: work items, uploaded at bind time
   size_t items_off = 0;
 };
@@ -285,9 +286,10 @@ extern "C" int tamm_sched_build(tamm_sched* s) {
   // reads directly), in their own workspace regions
   for (Node& n : s->nodes) {
     if (n.ops.size() < 2 || s->ops[n.ops[0]].kind != OP_ADD) continue;
-    const tamm_add* head = s->ops[n.ops[0]].add;
-    if (n.add_ydim < 0) n.add_ydim = add_out(head)->rank - 2;
-    const int rc = add_chain_items(head, n.add_ydim, n.add_items);
+    std::vector<const tamm_add*> m;
+    for (int i : n.ops) m.push_back(s->ops[i].add);
+    if (n.add_ydim < 0) n.add_ydim = add_out(m[0])->rank - 2;
+    const int rc = add_chain_items(m, n.add_ydim, n.add_items, &n.add_plane);
     if (rc != TAMM_OK) {
       sched_free(s);
       s->nodes.clear();
@@ -381,7 +383,7 @@ static int sched_enqueue(tamm_sched* s, hipStream_t st) {
           m.push_back(s->ops[i].add);
           alpha.push_back(s->ops[i].alpha);
         }
-        const int rc = add_chain_enqueue(m, alpha, s->ops[n.ops[0]].beta, n.add_ydim,
+        const int rc = add_chain_enqueue(m, alpha, s->ops[n.ops[0]].beta, n.add_ydim, n.add_plane,
                                          (const AddItem*)(s->ws + n.items_off), (int64_t)n.add_items.size(), st);
         if (rc != TAMM_OK) return rc;
         continue;

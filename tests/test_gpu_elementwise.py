@@ -131,12 +131,16 @@ def _odd_tiles_dropped(tiles, spins):
     return sum(spins[: len(spins) // 2]) == sum(spins[len(spins) // 2:]) and tiles[0] % 2 == 0
 
 
-@pytest.mark.parametrize("case", ["antisymmetriser", "first_virtual", "direct_only", "rank2"])
+@pytest.mark.parametrize("case", ["antisymmetriser", "plane_max", "plane_ragged", "first_virtual", "direct_only",
+                                  "rank2"])
 def test_scheduled_addop_chain_matches_oracle(case):
     # the scheduler runs consecutive AddOps into one out as one launch (an AddOp chain); ragged
-    # tiles on both spaces, terms read directly and through the LDS tile, beta of the first term;
-    # tile extents above 32 put several 32 x 32 work items on one plane of a block
-    prob = {"antisymmetriser": Problem(14, 22, 4, 5), "first_virtual": Problem(12, 90, 3, 37),
+    # tiles on both spaces, terms read directly and through LDS, beta of the first term.  Planes of
+    # the last two dimensions of at most 1024 elements run one plane per workgroup (32 x 32 = 1024
+    # at the limit; 16/14-row ragged planes); other chains take 32 x 32 tiles of their plane,
+    # several per plane where tile extents exceed 32
+    prob = {"antisymmetriser": Problem(14, 22, 4, 5), "plane_max": Problem(64, 20, 32, 10),
+            "plane_ragged": Problem(60, 20, 16, 10), "first_virtual": Problem(12, 90, 3, 37),
             "direct_only": Problem(76, 20, 35, 10), "rank2": Problem(76, 90, 35, 37)}[case]
     if case == "rank2":
         out, out_o = dense_pair(prob, "vo", 11)
@@ -147,10 +151,16 @@ def test_scheduled_addop_chain_matches_oracle(case):
         out, out_o = dense_pair(prob, "vvoo", 11)
         x, x_o = dense_pair(prob, "vvoo", 12)
         z, z_o = dense_pair(prob, "vvoo", 13)
-        if case == "antisymmetriser":  # the doubles residual's P(ij)P(ab) terms
+        if case in ("antisymmetriser", "plane_max"):  # the doubles residual's P(ij)P(ab) terms
             terms = [(x, x_o, "abij", "abij", 1.0, 0.0), (x, x_o, "abij", "abji", -1.0, 1.0),
                      (x, x_o, "abij", "baij", -1.0, 1.0), (x, x_o, "abij", "baji", 1.0, 1.0),
                      (z, z_o, "abij", "abij", 0.5, 1.0), (z, z_o, "abij", "abji", -0.5, 1.0)]
+        elif case == "plane_ragged":  # and an input with blocks of its own dropped
+            dense = np.random.default_rng(16).standard_normal(tuple(s.extent for s in x_o.spaces))
+            q = tm.Tensor([prob.g[c] for c in "vvoo"], nonzero=_odd_tiles_dropped).from_dense(dense)
+            q_o = oracle.BlockTensor.from_dense([prob.o[c] for c in "vvoo"], dense, nonzero=_odd_tiles_dropped)
+            terms = [(x, x_o, "abij", "baji", 1.0, 1.0), (q, q_o, "abij", "abji", -2.0, 1.0),
+                     (q, q_o, "abij", "baij", 0.5, 1.0), (z, z_o, "abij", "abij", 1.0, 1.0)]
         elif case == "first_virtual":  # transposed terms end in out's first label
             w, w_o = dense_pair(prob, "oovv", 14)
             dense = np.random.default_rng(15).standard_normal(tuple(s.extent for s in w_o.spaces))
