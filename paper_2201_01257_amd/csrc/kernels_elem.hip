@@ -1,6 +1,7 @@
 // HIP kernels for gfx950: the element-wise operations of the operation grammar -- SetOp (every
-// stored element takes one value) and AddOp (out = beta*out + alpha*in, in read through a label
-// permutation).  Both are bound by HBM bandwidth: each element is read and written once, with
+// stored element takes one value), AddOp (out = beta*out + alpha*in, in read through a label
+// permutation) and AddOp chains (several AddOps into one out in one pass, built by the
+// scheduler).  All are bound by HBM bandwidth: each element is read and written once, with
 // coalesced accesses on both sides.
 #include <hip/hip_runtime.h>
 
