@@ -454,8 +454,9 @@ int tamm_add_destroy(tamm_add* a);
  *     the output's last label or in the one other label that the chain's transposed members end
  *     in.  A chain is one node and one launch: out = beta_first*out + the members' alpha*in terms
  *     added in queue order, each output element read and written once (the antisymmetrisers
- *     P(ij)P(ab) written as permuted additions, Fig. 3).  Each product and partial sum is rounded
- *     once, as in the AddOps run one by one; the device may fuse a product into its sum.
+ *     P(ij)P(ab) written as permuted additions, Fig. 3).  Every product alpha*in and every
+ *     partial sum is rounded on its own (no fused multiply-add): the arithmetic of the AddOps
+ *     applied one after another in float64.
  *   - levels: nodes, in the order of their last queued operation, each go one level after the
  *     latest earlier node they conflict with (tensors compared by handle and by storage overlap).
  *   Every level runs as one group launch of its contraction nodes (screening, one persistent

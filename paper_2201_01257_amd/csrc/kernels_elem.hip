@@ -152,9 +152,12 @@ __global__ __launch_bounds__(256) void k_add_transpose(AddParams P) {
 // AddOp chain (several AddOps into one out, fused by the scheduler): one 32 x 32 tile of the
 // (ydim, last) plane per workgroup, as in k_add_transpose.  Every term's loads are issued before
 // any is used; a term whose in ends in out's last label is read along it, one whose in ends in
-// label ydim goes through the LDS tile.  The terms are added to beta*out in queue order.
+// label ydim goes through the LDS tile.  The terms are added to beta*out in queue order, each
+// product alpha*in and each sum rounded on its own (no fused multiply-add), which is the
+// arithmetic of the AddOps applied one after another.
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_add_multi(AddMultiParams P) {
+#pragma clang fp contract(off)  // every product and every sum rounded once, as AddOps one by one
   __shared__ double tile[kAddTile][kAddTile + 1];
   const int64_t it = blockIdx.x;
   if (it >= P.n_items) return;
@@ -238,6 +241,7 @@ __global__ __launch_bounds__(256) void k_add_multi(AddMultiParams P) {
 // transposed term (its plane stored [x][y]) is read contiguously too and turned through LDS,
 // stored with a row stride of ey + 1 doubles so that the transposed reads spread over the banks.
 __global__ __launch_bounds__(256) void k_add_multi_plane(AddMultiParams P) {
+#pragma clang fp contract(off)  // every product and every sum rounded once, as AddOps one by one
   __shared__ double tile[2 * kAddPlaneMax];
   const int64_t it = blockIdx.x;
   if (it >= P.n_items) return;
